@@ -1,0 +1,120 @@
+// Types shared by the host runtime and the HIP kernels of libwtpic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.hpp"
+
+namespace wtpic {
+
+// Precision policies.  F32: int32 cell + FP32 offsets, FP32 momenta, fields,
+// weights and per-tile current.  F64: absolute FP64 positions, FP64 everywhere.
+struct F32 {
+  using Real = float;
+  using Acc = float;
+  static constexpr bool kAbs = false;
+};
+struct F64 {
+  using Real = double;
+  using Acc = double;
+  static constexpr bool kAbs = true;
+};
+
+// Packed cell coordinates of the FP32 layout: 2D x | y << 16 (n < 65536),
+// 3D x | y << 11 | z << 22 (n < 2048).
+template <int DIM>
+__host__ __device__ inline int pack_cell(int x, int y, int z) {
+  if (DIM == 2) return x | (y << 16);
+  return x | (y << 11) | (z << 22);
+}
+template <int DIM>
+__host__ __device__ inline void unpack_cell(int c, int& x, int& y, int& z) {
+  if (DIM == 2) {
+    x = c & 0xffff;
+    y = (c >> 16) & 0xffff;
+    z = 0;
+  } else {
+    x = c & 0x7ff;
+    y = (c >> 11) & 0x7ff;
+    z = (c >> 22) & 0x3ff;
+  }
+}
+
+// Per-run constants, one entry per run in device memory.
+template <class Real>
+struct RunDev {
+  int n[3];           // cells per axis (n[2] = 1 in 2D)
+  int ntile[3];       // tiles per axis
+  int tile0;          // global index of the run's first tile
+  int KT;             // nodes of the T table (max over axes)
+  long long cell0;    // offset of the run's cells in the concatenated grids
+  long long p0;       // offset of the run's particles in the particle stores
+  long long np;       // particles of both species
+  int glo[3], ghi[3]; // gather stencil reach (node offsets from the cell)
+  int dlo[3], dhi[3]; // deposit stencil reach (old or new position)
+  Real a[3];          // c dt / dx_d
+  Real eps[2];        // (q/m) dt / (2 c) per species
+  Real c;             // speed of light
+  Real dt;            // time step
+  Real hcdt;          // c dt / 2 (Faraday half step)
+  Real inv_dx[3];     // 1 / dx_d
+  Real m4beta[3][3];  // M4 Faraday coefficients (0 for Yee): [d][e]
+  double js[2][3];    // current scale per species: -Q dx_d/(Vc dt); J3 in 2D: Q c/Vc
+  double Vc;          // cell volume
+  double dxd[3];      // cell sizes
+  double Q[2];        // macro charge per species
+  double M[2];        // macro mass per species
+  Tab<Real> Wh[3];    // W_l on the half-integer lattice
+  Tab<Real> Wi[3];    // W_l on the integer lattice (charge form factor)
+  Tab<Real> T[3];     // T_l (WT) or W_l (MC) on the integer lattice
+};
+
+// One of the two particle stores.
+template <class Real>
+struct PBuf {
+  int* cell;      // packed cell (F32 layout only)
+  Real* pos[3];   // F32: in-cell offsets; F64: absolute positions (cell units)
+  Real* u[3];     // momenta u = gamma v / c
+  int* tag;       // species << 30 | index within (run, species)
+};
+
+constexpr int kSpeciesShift = 30;
+
+// Device-side mutable state of a context.
+struct DevState {
+  int parity;                  // current particle store
+  int sort_request;            // set when a tile's particles outgrew the staging margin
+  int sort_active;             // the sort sequence in flight works
+  int pad;
+  unsigned long long n_nonfinite;
+  unsigned long long n_out_of_range;
+  unsigned long long n_sorts;
+  unsigned long long pad2;
+};
+
+template <class Real>
+struct GpdArgs {
+  const RunDev<Real>* runs;
+  const int* tile_run;   // run of each global tile
+  const int* seg;        // 2G+1 segment offsets: key 2g+s covers [seg[key], seg[key+1])
+  int* bbox;             // per tile: lo0, hi0, lo1, hi1, lo2, hi2 (cells, tile-relative)
+  DevState* st;
+  PBuf<Real> buf[2];
+  const Real* F;         // E1 E2 E3 B1 B2 B3, each ncell_total
+  double* J;             // J1 J2 J3, each ncell_total
+  long long ncell_total;
+  int G;                 // tiles in all runs
+  int tile[3];           // tile size (cells)
+  int fw[3];             // field window capacity (nodes)
+  int jw[3];             // current window capacity (nodes)
+  int guard[3];          // bbox extent above which a re-sort is requested
+};
+
+// Position of a (possibly negative or >= n) lattice index on a periodic axis.
+__host__ __device__ inline int wrapi(int m, int n) {
+  m %= n;
+  return m < 0 ? m + n : m;
+}
+
+}  // namespace wtpic

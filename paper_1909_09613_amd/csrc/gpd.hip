@@ -1,0 +1,617 @@
+// Gather + Boris push + Esirkepov deposit for one tile's particles per
+// workgroup (gfx950, wave64, no MFMA: nothing here is a dense contraction).
+//
+// A workgroup owns one tile g (a rectangle of cells of one run) and the two
+// particle segments (electrons, positrons) the last counting sort assigned to
+// it.  The particles have drifted since that sort; the tile keeps the
+// bounding box of its particles' cells (tile-relative, refreshed by every
+// step), and the workgroup stages E and B on that box plus the gather reach
+// into LDS, accumulates the current of the box plus the deposit reach in an
+// LDS tile, and flushes that tile to the FP64 global current with one atomic
+// add per node.  When a box outgrows the staging margin the tile requests a
+// re-sort, which the next sort pass performs before the box can overflow.
+//
+// Per particle (Sec. 2 and the methods it cites):
+//   gather   Eq. interpolation-EB-real-mod: along an axis on which a component
+//            is staggered the B-spline W_l on the half-integer lattice, across
+//            it T_l (WT) or W_l (MC) on the integer lattice.  In 2D the x3
+//            factor is one (nothing depends on x3, both kernels sum to one).
+//            (E1, B2) and (E2, B1) share lattice and weights in 2D and are
+//            staged as pairs.
+//   push     relativistic Boris: half kick, rotation, half kick.
+//   move     x~ += (c dt/dx) u / gamma; FP32 keeps cell + offset in [0,1).
+//   deposit  form-factor differences DS = S1 - S0 on the union of old and
+//            new nodes, evaluated as step * divided difference so that short
+//            transverse steps keep their precision in FP32; Esirkepov's
+//            decomposition W_x = DS_x (S0_y + DS_y/2) etc., prefix sums along
+//            each component's own axis.
+#include <climits>
+#include <type_traits>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace wtpic {
+
+namespace {
+
+template <class Real>
+struct Pair;
+template <>
+struct Pair<float> {
+  using T = float2;
+};
+template <>
+struct Pair<double> {
+  using T = double2;
+};
+
+// Sum over a 3D stencil of a staged component: weights along x, y, z are wx
+// (NX nodes), wy (NY), wz (NZ); ox, oy, oz the window index of the first node.
+template <int NX, int NY, int NZ, class Real>
+__device__ __forceinline__ Real gather3(const Real* Fc, int fwx, int fwy, const Real* wx, const Real* wy,
+                                        const Real* wz, int ox, int oy, int oz) {
+  Real s = Real(0);
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    Real sy = Real(0);
+#pragma unroll
+    for (int j = 0; j < NY; ++j) {
+      const Real* row = Fc + ox + fwx * (oy + j + fwy * (oz + k));
+      Real sx = Real(0);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) sx += wx[i] * row[i];
+      sy += wy[j] * sx;
+    }
+    s += wz[k] * sy;
+  }
+  return s;
+}
+
+template <class Real>
+__device__ __forceinline__ bool finite3(Real a, Real b, Real c) {
+  return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+template <class Acc>
+__device__ __forceinline__ void lds_add(Acc* p, Acc v) {
+  atomicAdd(p, v);
+}
+
+}  // namespace
+
+template <class P, int L, int DIM, int KT>
+__device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, const int g,
+                                         unsigned char* lds, int* sred) {
+  using Real = typename P::Real;
+  using Acc = typename P::Acc;
+  using Real2 = typename Pair<Real>::T;
+  constexpr int NW = L + 1;  // W nodes
+  constexpr int NU = L + 2;  // union of old and new form-factor nodes
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+
+  const int r = A.tile_run[g];
+  const RunDev<Real>& R = A.runs[r];
+  const int lt = g - R.tile0;
+  int org[3];
+  org[0] = (lt % R.ntile[0]) * A.tile[0];
+  org[1] = ((lt / R.ntile[0]) % R.ntile[1]) * A.tile[1];
+  org[2] = (DIM == 3) ? (lt / (R.ntile[0] * R.ntile[1])) * A.tile[2] : 0;
+
+  int bb[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) bb[i] = A.bbox[g * 6 + i];
+  int fo[3] = {0, 0, 0}, fs[3] = {1, 1, 1}, jo[3] = {0, 0, 0}, jsz[3] = {1, 1, 1};
+  bool fits = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    fo[d] = bb[2 * d] + R.glo[d];
+    fs[d] = bb[2 * d + 1] + R.ghi[d] - fo[d] + 1;
+    jo[d] = bb[2 * d] + R.dlo[d];
+    jsz[d] = bb[2 * d + 1] + R.dhi[d] - jo[d] + 1;
+    fits = fits && fs[d] >= 1 && jsz[d] >= 1 && fs[d] <= A.fw[d] && jsz[d] <= A.jw[d];
+  }
+  const int sA = A.seg[2 * g], sB = A.seg[2 * g + 1], sC = A.seg[2 * g + 2];
+  if (!fits) {
+    // cannot happen while the re-sort guard holds; report and leave the tile
+    if (tid == 0) {
+      atomicAdd(&A.st->n_out_of_range, (unsigned long long)(sC - sA));
+      atomicOr(&A.st->sort_request, 1);
+    }
+    return;
+  }
+
+  const int fwx = A.fw[0], fwy = A.fw[1];
+  const int fcap = fwx * fwy * (DIM == 3 ? A.fw[2] : 1);
+  const int jwx = A.jw[0], jwy = A.jw[1];
+  const int jcap = jwx * jwy * (DIM == 3 ? A.jw[2] : 1);
+  const long long NT = A.ncell_total;
+  const Real* Fg = A.F + R.cell0;
+
+  Real2* P1 = nullptr;
+  Real2* P2 = nullptr;
+  Real* P3 = nullptr;
+  Real* P4 = nullptr;
+  Real* F6 = nullptr;
+  Acc* Jl;
+  if (DIM == 2) {
+    P1 = reinterpret_cast<Real2*>(lds);
+    P2 = P1 + fcap;
+    P3 = reinterpret_cast<Real*>(P2 + fcap);
+    P4 = P3 + fcap;
+    Jl = reinterpret_cast<Acc*>(P4 + fcap);
+  } else {
+    F6 = reinterpret_cast<Real*>(lds);
+    Jl = reinterpret_cast<Acc*>(F6 + 6 * fcap);
+  }
+
+  // ---- stage E, B on the window; clear the current tile ------------------
+  const int nfs = fs[0] * fs[1] * fs[2];
+  for (int i = tid; i < nfs; i += nth) {
+    const int w0 = i % fs[0];
+    const int q = i / fs[0];
+    const int w1 = q % fs[1];
+    const int w2 = q / fs[1];
+    const int gx = wrapi(org[0] + fo[0] + w0, R.n[0]);
+    const int gy = wrapi(org[1] + fo[1] + w1, R.n[1]);
+    const int gz = (DIM == 3) ? wrapi(org[2] + fo[2] + w2, R.n[2]) : 0;
+    const long long gi = gx + (long long)R.n[0] * (gy + (long long)R.n[1] * gz);
+    const int li = w0 + fwx * (w1 + fwy * w2);
+    if (DIM == 2) {
+      Real2 a, b;
+      a.x = Fg[0 * NT + gi];
+      a.y = Fg[4 * NT + gi];
+      b.x = Fg[1 * NT + gi];
+      b.y = Fg[3 * NT + gi];
+      P1[li] = a;
+      P2[li] = b;
+      P3[li] = Fg[2 * NT + gi];
+      P4[li] = Fg[5 * NT + gi];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) F6[c * fcap + li] = Fg[c * NT + gi];
+    }
+  }
+  for (int i = tid; i < 3 * jcap; i += nth) Jl[i] = Acc(0);
+  if (tid < 6) sred[tid] = (tid & 1) ? INT_MIN : INT_MAX;
+  if (tid == 6 || tid == 7) sred[tid] = 0;
+  __syncthreads();
+
+  const PBuf<Real> B = A.buf[A.st->parity];
+  int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
+  int nbad = 0, noor = 0;
+  const Real third = Real(1) / Real(3);
+  const Real half = Real(0.5);
+
+  for (int p = sA + tid; p < sC; p += nth) {
+    const int sp = (p >= sB) ? 1 : 0;
+    // ---- load ---------------------------------------------------------
+    int c[3] = {0, 0, 0};
+    Real f[3] = {Real(0), Real(0), Real(0)};
+    Real xo[3] = {Real(0), Real(0), Real(0)};
+    if (P::kAbs) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        xo[d] = B.pos[d][p];
+        const Real fl = floor(xo[d]);
+        c[d] = (int)fl;
+        f[d] = xo[d] - fl;
+      }
+    } else {
+      unpack_cell<DIM>(B.cell[p], c[0], c[1], c[2]);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) f[d] = B.pos[d][p];
+    }
+    Real u0 = B.u[0][p], u1 = B.u[1][p], u2 = B.u[2][p];
+
+    int rel[3] = {0, 0, 0};
+    bool inwin = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int n = R.n[d];
+      int rr = c[d] - org[d];
+      if (rr >= (n + 1) / 2) rr -= n;
+      else if (rr < -(n / 2)) rr += n;
+      rel[d] = rr;
+      inwin = inwin && (rr + R.glo[d] >= fo[d]) && (rr + R.ghi[d] < fo[d] + fs[d]) &&
+              (rr + R.dlo[d] >= jo[d]) && (rr + R.dhi[d] < jo[d] + jsz[d]);
+    }
+    if (!inwin) {
+      ++noor;
+      continue;
+    }
+
+    // ---- weights at x^n --------------------------------------------------
+    Real wh[3][NW], wt[3][KT];
+    int ih[3] = {0, 0, 0}, it[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int b;
+      Real gg;
+      tab_split(R.Wh[d], c[d], f[d], b, gg);
+      tab_eval<L, NW, false>(R.Wh[d], gg, wh[d]);
+      ih[d] = rel[d] + (b - c[d]) + R.Wh[d].first - fo[d];
+      tab_split(R.T[d], c[d], f[d], b, gg);
+      tab_eval<L, KT, true>(R.T[d], gg, wt[d]);
+      it[d] = rel[d] + (b - c[d]) + R.T[d].first - fo[d];
+    }
+
+    // ---- gather ------------------------------------------------------------
+    Real E0, E1, E2, B0, B1, B2;
+    if (DIM == 2) {
+      // (E1, B2): W along x (half lattice), T along y
+      E0 = B1 = Real(0);
+#pragma unroll
+      for (int j = 0; j < KT; ++j) {
+        const Real2* row = P1 + ih[0] + fwx * (it[1] + j);
+        Real se = Real(0), sb = Real(0);
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const Real2 v = row[i];
+          se += wh[0][i] * v.x;
+          sb += wh[0][i] * v.y;
+        }
+        E0 += wt[1][j] * se;
+        B1 += wt[1][j] * sb;
+      }
+      // (E2, B1): T along x, W along y (half lattice)
+      E1 = B0 = Real(0);
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const Real2* row = P2 + it[0] + fwx * (ih[1] + j);
+        Real se = Real(0), sb = Real(0);
+#pragma unroll
+        for (int i = 0; i < KT; ++i) {
+          const Real2 v = row[i];
+          se += wt[0][i] * v.x;
+          sb += wt[0][i] * v.y;
+        }
+        E1 += wh[1][j] * se;
+        B0 += wh[1][j] * sb;
+      }
+      const Real one = Real(1);
+      E2 = gather3<KT, KT, 1>(P3, fwx, fwy, wt[0], wt[1], &one, it[0], it[1], 0);
+      B2 = gather3<NW, NW, 1>(P4, fwx, fwy, wh[0], wh[1], &one, ih[0], ih[1], 0);
+    } else {
+      E0 = gather3<NW, KT, KT>(F6 + 0 * fcap, fwx, fwy, wh[0], wt[1], wt[2], ih[0], it[1], it[2]);
+      E1 = gather3<KT, NW, KT>(F6 + 1 * fcap, fwx, fwy, wt[0], wh[1], wt[2], it[0], ih[1], it[2]);
+      E2 = gather3<KT, KT, NW>(F6 + 2 * fcap, fwx, fwy, wt[0], wt[1], wh[2], it[0], it[1], ih[2]);
+      B0 = gather3<KT, NW, NW>(F6 + 3 * fcap, fwx, fwy, wt[0], wh[1], wh[2], it[0], ih[1], ih[2]);
+      B1 = gather3<NW, KT, NW>(F6 + 4 * fcap, fwx, fwy, wh[0], wt[1], wh[2], ih[0], it[1], ih[2]);
+      B2 = gather3<NW, NW, KT>(F6 + 5 * fcap, fwx, fwy, wh[0], wh[1], wt[2], ih[0], ih[1], it[2]);
+    }
+
+    // ---- Boris -------------------------------------------------------------
+    const Real eps = R.eps[sp];
+    const Real umx = u0 + eps * E0, umy = u1 + eps * E1, umz = u2 + eps * E2;
+    const Real igm = Real(1) / sqrt(Real(1) + umx * umx + umy * umy + umz * umz);
+    const Real tx = eps * B0 * igm, ty = eps * B1 * igm, tz = eps * B2 * igm;
+    const Real s2 = Real(2) / (Real(1) + tx * tx + ty * ty + tz * tz);
+    const Real sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
+    const Real upx = umx + (umy * tz - umz * ty);
+    const Real upy = umy + (umz * tx - umx * tz);
+    const Real upz = umz + (umx * ty - umy * tx);
+    const Real n0 = umx + (upy * sz - upz * sy) + eps * E0;
+    const Real n1 = umy + (upz * sx - upx * sz) + eps * E1;
+    const Real n2 = umz + (upx * sy - upy * sx) + eps * E2;
+    if (!finite3(n0, n1, n2)) {
+      ++nbad;
+      // leave the particle where it is; its box entry keeps the window valid
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        bmin[d] = min(bmin[d], rel[d]);
+        bmax[d] = max(bmax[d], rel[d]);
+      }
+      continue;
+    }
+    u0 = n0;
+    u1 = n1;
+    u2 = n2;
+
+    // ---- move ------------------------------------------------------------
+    const Real igam = Real(1) / sqrt(Real(1) + u0 * u0 + u1 * u1 + u2 * u2);
+    const Real vv[3] = {u0 * igam, u1 * igam, u2 * igam};
+    int cn[3] = {0, 0, 0};
+    Real fn[3] = {Real(0), Real(0), Real(0)}, dd[3] = {Real(0), Real(0), Real(0)};
+    Real xw[3] = {Real(0), Real(0), Real(0)};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const Real step = R.a[d] * vv[d];
+      if (P::kAbs) {
+        const Real xn = xo[d] + step;
+        const Real fl = floor(xn);
+        cn[d] = (int)fl;
+        fn[d] = xn - fl;
+        dd[d] = xn - xo[d];
+        Real w = xn;
+        const Real nd = Real(R.n[d]);
+        while (w < Real(0)) w += nd;
+        while (w >= nd) w -= nd;
+        xw[d] = w;
+      } else {
+        Real t = f[d] + step;
+        int dc = 0;
+        if (t >= Real(1)) {
+          t -= Real(1);
+          dc = 1;
+        } else if (t < Real(0)) {
+          t += Real(1);
+          dc = -1;
+          if (t >= Real(1)) {
+            t = Real(0);
+            dc = 0;
+          }
+        }
+        fn[d] = t;
+        cn[d] = c[d] + dc;
+        dd[d] = (t - f[d]) + Real(dc);
+      }
+    }
+
+    // ---- form factors and their differences on the union stencil -----------
+    Real S0u[3][NU], DSu[3][NU];
+    int iu[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const Tab<Real>& Tw = R.Wi[d];
+      int b0, b1;
+      Real g0, g1;
+      tab_split(Tw, c[d], f[d], b0, g0);
+      tab_split(Tw, cn[d], fn[d], b1, g1);
+      Real s0[NW], dA[NW], dB[NW];
+      tab_eval<L, NW, false>(Tw, g0, s0);
+      const int db = b1 - b0;
+      const Real eA = (db == 0) ? g1 : (db > 0 ? Real(1) : Real(0));
+      const Real lA = (db == 0) ? dd[d] : (db > 0 ? Real(1) - g0 : -g0);
+      tab_diff<L>(Tw, g0, eA, lA, dA);
+      if (db != 0) {
+        const Real sBv = (db > 0) ? Real(0) : Real(1);
+        const Real lB = (db > 0) ? g1 : g1 - Real(1);
+        tab_diff<L>(Tw, sBv, g1, lB, dB);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) dB[k] = Real(0);
+      }
+      const bool shA = db < 0, shB = db > 0;
+#pragma unroll
+      for (int k = 0; k < NU; ++k) {
+        const Real a0 = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));
+        const Real da = shA ? (k >= 1 ? dA[k - 1] : Real(0)) : (k < NW ? dA[k] : Real(0));
+        const Real dbv = shB ? (k >= 1 ? dB[k - 1] : Real(0)) : (k < NW ? dB[k] : Real(0));
+        S0u[d][k] = a0;
+        DSu[d][k] = da + dbv;
+      }
+      iu[d] = rel[d] + (min(b0, b1) - c[d]) + Tw.first - jo[d];
+    }
+
+    // ---- Esirkepov current into the LDS tile -----------------------------
+    const Real jx = Real(R.js[sp][0]), jy = Real(R.js[sp][1]), jz = Real(R.js[sp][2]);
+    Acc* J0 = Jl;
+    Acc* J1 = Jl + jcap;
+    Acc* J2 = Jl + 2 * jcap;
+    if (DIM == 2) {
+#pragma unroll
+      for (int v = 0; v < NU; ++v) {
+        const Real fy = S0u[1][v] + half * DSu[1][v];
+        Acc* row = J0 + iu[0] + jwx * (iu[1] + v);
+        Real acc = Real(0);
+#pragma unroll
+        for (int u = 0; u <= L; ++u) {
+          acc += DSu[0][u] * fy;
+          lds_add<Acc>(row + u, Acc(jx * acc));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const Real fx = S0u[0][u] + half * DSu[0][u];
+        Acc* col = J1 + iu[0] + u + jwx * iu[1];
+        Real acc = Real(0);
+#pragma unroll
+        for (int v = 0; v <= L; ++v) {
+          acc += DSu[1][v] * fx;
+          lds_add<Acc>(col + jwx * v, Acc(jy * acc));
+        }
+      }
+      const Real vz = jz * vv[2];
+#pragma unroll
+      for (int v = 0; v < NU; ++v) {
+        const Real Av = S0u[1][v] + half * DSu[1][v];
+        const Real Bv = half * S0u[1][v] + third * DSu[1][v];
+        Acc* row = J2 + iu[0] + jwx * (iu[1] + v);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) lds_add<Acc>(row + u, Acc(vz * (S0u[0][u] * Av + DSu[0][u] * Bv)));
+      }
+    } else {
+      // J1: prefix along x of DS_x * T_yz
+#pragma unroll
+      for (int w = 0; w < NU; ++w) {
+#pragma unroll
+        for (int v = 0; v < NU; ++v) {
+          const Real tr = S0u[1][v] * (S0u[2][w] + half * DSu[2][w]) +
+                          DSu[1][v] * (half * S0u[2][w] + third * DSu[2][w]);
+          Acc* row = J0 + iu[0] + jwx * (iu[1] + v + jwy * (iu[2] + w));
+          Real acc = Real(0);
+#pragma unroll
+          for (int u = 0; u <= L; ++u) {
+            acc += DSu[0][u] * tr;
+            lds_add<Acc>(row + u, Acc(jx * acc));
+          }
+        }
+      }
+      // J2: prefix along y of DS_y * T_xz
+#pragma unroll
+      for (int w = 0; w < NU; ++w) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const Real tr = S0u[0][u] * (S0u[2][w] + half * DSu[2][w]) +
+                          DSu[0][u] * (half * S0u[2][w] + third * DSu[2][w]);
+          Acc* col = J1 + iu[0] + u + jwx * (iu[1] + jwy * (iu[2] + w));
+          Real acc = Real(0);
+#pragma unroll
+          for (int v = 0; v <= L; ++v) {
+            acc += DSu[1][v] * tr;
+            lds_add<Acc>(col + jwx * v, Acc(jy * acc));
+          }
+        }
+      }
+      // J3: prefix along z of DS_z * T_xy
+#pragma unroll
+      for (int v = 0; v < NU; ++v) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const Real tr = S0u[0][u] * (S0u[1][v] + half * DSu[1][v]) +
+                          DSu[0][u] * (half * S0u[1][v] + third * DSu[1][v]);
+          Acc* col = J2 + iu[0] + u + jwx * (iu[1] + v + jwy * iu[2]);
+          Real acc = Real(0);
+#pragma unroll
+          for (int w = 0; w <= L; ++w) {
+            acc += DSu[2][w] * tr;
+            lds_add<Acc>(col + jwx * jwy * w, Acc(jz * acc));
+          }
+        }
+      }
+    }
+
+    // ---- store, box --------------------------------------------------------
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int rn = rel[d] + (cn[d] - c[d]);
+      bmin[d] = min(bmin[d], rn);
+      bmax[d] = max(bmax[d], rn);
+    }
+    if (P::kAbs) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) B.pos[d][p] = xw[d];
+    } else {
+      int cw[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        int m = cn[d];
+        if (m < 0) m += R.n[d];
+        else if (m >= R.n[d]) m -= R.n[d];
+        cw[d] = m;
+        B.pos[d][p] = fn[d];
+      }
+      B.cell[p] = pack_cell<DIM>(cw[0], cw[1], cw[2]);
+    }
+    B.u[0][p] = u0;
+    B.u[1][p] = u1;
+    B.u[2][p] = u2;
+  }
+
+  // ---- box and counters: wave reduction, then one LDS atomic per wave ------
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      bmin[d] = min(bmin[d], __shfl_xor(bmin[d], off));
+      bmax[d] = max(bmax[d], __shfl_xor(bmax[d], off));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    nbad += __shfl_xor(nbad, off);
+    noor += __shfl_xor(noor, off);
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      atomicMin(&sred[2 * d], bmin[d]);
+      atomicMax(&sred[2 * d + 1], bmax[d]);
+    }
+    if (nbad) atomicAdd(&sred[6], nbad);
+    if (noor) atomicAdd(&sred[7], noor);
+  }
+  __syncthreads();
+
+  // ---- flush the current tile ------------------------------------------------
+  double* Jg = A.J + R.cell0;
+  const int njs = jsz[0] * jsz[1] * jsz[2];
+  for (int i = tid; i < njs; i += nth) {
+    const int w0 = i % jsz[0];
+    const int q = i / jsz[0];
+    const int w1 = q % jsz[1];
+    const int w2 = q / jsz[1];
+    const int gx = wrapi(org[0] + jo[0] + w0, R.n[0]);
+    const int gy = wrapi(org[1] + jo[1] + w1, R.n[1]);
+    const int gz = (DIM == 3) ? wrapi(org[2] + jo[2] + w2, R.n[2]) : 0;
+    const long long gi = gx + (long long)R.n[0] * (gy + (long long)R.n[1] * gz);
+    const int li = w0 + jwx * (w1 + jwy * w2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const Acc v = Jl[c * jcap + li];
+      if (v != Acc(0)) unsafeAtomicAdd(Jg + c * NT + gi, (double)v);
+    }
+  }
+
+  if (tid == 0) {
+    bool need = false;
+    for (int d = 0; d < 3; ++d) {
+      int lo = 0, hi = 0;
+      if (d < DIM) {
+        lo = sred[2 * d];
+        hi = sred[2 * d + 1];
+        if (lo > hi) {  // no particles: keep the tile rectangle
+          lo = 0;
+          hi = min(A.tile[d], R.n[d] - org[d]) - 1;
+        }
+        need = need || (hi - lo > A.guard[d]);
+      }
+      A.bbox[g * 6 + 2 * d] = lo;
+      A.bbox[g * 6 + 2 * d + 1] = hi;
+    }
+    if (need) atomicOr(&A.st->sort_request, 1);
+    if (sred[6]) atomicAdd(&A.st->n_nonfinite, (unsigned long long)sred[6]);
+    if (sred[7]) atomicAdd(&A.st->n_out_of_range, (unsigned long long)sred[7]);
+  }
+}
+
+template <class P, int L, int DIM>
+__global__ void __launch_bounds__(256) gpd_kernel(GpdArgs<typename P::Real> A) {
+  extern __shared__ __align__(16) unsigned char lds_dyn[];
+  __shared__ int sred[8];
+  // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of tiles so neighbouring windows share its L2.
+  const int b = blockIdx.x;
+  const int per = gridDim.x >> 3;
+  const int g = (b & 7) * per + (b >> 3);
+  if (g >= A.G) return;
+  const int kt = A.runs[A.tile_run[g]].KT;
+  if (kt == L + 1)
+    gpd_tile<P, L, DIM, L + 1>(A, g, lds_dyn, sred);
+  else
+    gpd_tile<P, L, DIM, L + 2>(A, g, lds_dyn, sred);
+}
+
+template <class P, int L, int DIM>
+static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
+  const int grid = ((a.G + 7) / 8) * 8;
+  hipLaunchKernelGGL((gpd_kernel<P, L, DIM>), dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, size_t lds, hipStream_t s) {
+  if (ndim == 2) {
+    switch (order) {
+      case 1: return launch_one<P, 1, 2>(a, lds, s);
+      case 2: return launch_one<P, 2, 2>(a, lds, s);
+      case 3: return launch_one<P, 3, 2>(a, lds, s);
+      case 4: return launch_one<P, 4, 2>(a, lds, s);
+    }
+  } else {
+    switch (order) {
+      case 1: return launch_one<P, 1, 3>(a, lds, s);
+      case 2: return launch_one<P, 2, 3>(a, lds, s);
+      case 3: return launch_one<P, 3, 3>(a, lds, s);
+      case 4: return launch_one<P, 4, 3>(a, lds, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_gpd<F32>(const GpdArgs<float>&, int, int, size_t, hipStream_t);
+template hipError_t launch_gpd<F64>(const GpdArgs<double>&, int, int, size_t, hipStream_t);
+
+}  // namespace wtpic

@@ -1,0 +1,68 @@
+// Host-side launchers of the HIP kernels (defined in the .hip sources).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace wtpic {
+
+template <class Real>
+struct SortArgs {
+  const RunDev<Real>* runs;
+  int nruns;
+  DevState* st;
+  PBuf<Real> buf[2];
+  long long np_total;
+  int G;
+  int nkeys;          // 2 G
+  int tile[3];
+  int* counts;        // nkeys
+  int* cursor;        // nkeys
+  int* seg;           // nkeys + 1
+  int* keys;          // np_total
+  int* bbox;          // 6 G
+  const int* tile_run;
+};
+
+template <class Real>
+struct FieldArgs {
+  const RunDev<Real>* runs;
+  const int* blk_run;      // run of each block of a grid-wide cell launch
+  const int* blk_first;    // first cell (within its run) of each block
+  Real* F;                 // E1 E2 E3 B1 B2 B3, each ncell_total
+  double* J;               // J1 J2 J3
+  long long ncell_total;
+  int nblocks;
+};
+
+template <class Real>
+struct DiagArgs {
+  const RunDev<Real>* runs;
+  int run;
+  DevState* st;
+  PBuf<Real> buf[2];
+  const Real* F;
+  long long ncell_total;
+  double* acc;             // 16 accumulators (see diag kernels)
+  double* rho;             // ncell of the run
+};
+
+template <class P>
+hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, size_t lds, hipStream_t s);
+
+template <class P>
+hipError_t launch_sort(const SortArgs<typename P::Real>& a, int ndim, hipStream_t s);
+
+template <class Real>
+hipError_t launch_faraday_half(const FieldArgs<Real>& a, int ndim, bool m4, hipStream_t s);
+template <class Real>
+hipError_t launch_ampere(const FieldArgs<Real>& a, int ndim, hipStream_t s);
+template <class Real>
+hipError_t launch_fill(Real* p, long long n, Real v, hipStream_t s);
+
+template <class P>
+hipError_t launch_diag(const DiagArgs<typename P::Real>& a, int ndim, int order, long long cells,
+                       long long p0, long long np, hipStream_t s);
+
+}  // namespace wtpic

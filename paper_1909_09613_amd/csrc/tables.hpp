@@ -1,0 +1,113 @@
+// Per-axis interpolation tables: the B-spline W_l and the WT factor T_l as
+// polynomials in the in-cell coordinate.
+//
+// A particle at x~ (cell units) is split as x~ = base + sigma + g with
+// base = floor(x~ - sigma) and g in [0, 1).  sigma is chosen per kernel so
+// that all its nodes' weights are polynomials in g on [0, 1): for W_l no knot
+// falls inside, for T_l exactly one (at kappa).  Node k (k = 0..K-1) is the
+// lattice index base + first + k and carries
+//     w_k(g) = sum_r c[k][r] g^r + alpha[k] * max(g - kappa, 0)^l.
+// The tables are built on the host from the truncated-power form of each
+// kernel (tables.cpp); the same evaluator runs on the host (table tests) and
+// in the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace wtpic {
+
+constexpr int kMaxNodes = 6;   // l + 2 for l = 4
+constexpr int kMaxCoef = 5;    // degree l + 1 coefficients for l = 4
+
+template <class Real>
+struct Tab {
+  Real sigma;                   // lattice shift of the split
+  Real one_minus_sigma;         // 1 - sigma, so that g = f + (1 - sigma) rounds once
+  Real kappa;                   // interior knot in g (>= 1 when there is none)
+  int first;                    // node offset from base
+  int K;                        // node count
+  Real c[kMaxNodes][kMaxCoef];  // polynomial coefficients, c[k][r] of g^r
+  Real alpha[kMaxNodes];        // coefficient of the knot term
+};
+
+// Split a position given as (cell, in-cell offset f in [0,1)) for a table.
+template <class Real>
+__host__ __device__ inline void tab_split(const Tab<Real>& t, int cell, Real f, int& base, Real& g) {
+  if (f >= t.sigma) {
+    base = cell;
+    g = f - t.sigma;
+  } else {
+    base = cell - 1;
+    g = f + t.one_minus_sigma;
+  }
+}
+
+template <class Real>
+__host__ __device__ inline Real ipow(Real x, int l) {
+  Real r = x;
+  for (int i = 1; i < l; ++i) r *= x;
+  return r;
+}
+
+// Weights w[0..K-1] at in-frame coordinate g (L = order, K = node count).
+template <int L, int K, bool KNOT, class Real>
+__host__ __device__ inline void tab_eval(const Tab<Real>& t, Real g, Real* w) {
+  Real tk = 0;
+  if (KNOT) {
+    Real d = g - t.kappa;
+    d = d > Real(0) ? d : Real(0);
+    tk = ipow(d, L);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    Real acc = t.c[k][L];
+#pragma unroll
+    for (int r = L - 1; r >= 0; --r) acc = acc * g + t.c[k][r];
+    if (KNOT) acc += t.alpha[k] * tk;
+    w[k] = acc;
+  }
+}
+
+// Weight differences w_k(e) - w_k(g) = (e - g) * sum_{r>=1} c[k][r] h_r(g, e),
+// h_r = sum_{i+j=r-1} g^i e^j, written as d * (divided difference) so that a
+// short step d = e - g keeps full relative precision.  Knot-free tables only.
+template <int L, class Real>
+__host__ __device__ inline void tab_diff(const Tab<Real>& t, Real g, Real e, Real d, Real* dw) {
+  Real h[kMaxCoef];
+  h[1] = Real(1);
+  Real gp = g;  // g^(r-1)
+#pragma unroll
+  for (int r = 2; r <= L; ++r) {
+    h[r] = h[r - 1] * e + gp;
+    gp *= g;
+  }
+#pragma unroll
+  for (int k = 0; k <= L; ++k) {
+    Real acc = t.c[k][L] * h[L];
+#pragma unroll
+    for (int r = L - 1; r >= 1; --r) acc += t.c[k][r] * h[r];
+    dw[k] = d * acc;
+  }
+}
+
+// Host: build the table of one kernel kind for order l.
+//   kind 0: W_l on the half-integer lattice (nodes at m + 1/2)
+//   kind 1: W_l on the integer lattice
+//   kind 2: T_l(.; a) on the integer lattice, 0 < a < 1
+// Returns false (and a message) on invalid input or an internal inconsistency.
+bool build_table(int l, int kind, double a, Tab<double>& out, const char** err);
+
+template <class Real>
+inline void convert_table(const Tab<double>& in, Tab<Real>& out) {
+  out.sigma = Real(in.sigma);
+  out.one_minus_sigma = Real(in.one_minus_sigma);
+  out.kappa = Real(in.kappa);
+  out.first = in.first;
+  out.K = in.K;
+  for (int k = 0; k < kMaxNodes; ++k) {
+    for (int r = 0; r < kMaxCoef; ++r) out.c[k][r] = Real(in.c[k][r]);
+    out.alpha[k] = Real(in.alpha[k]);
+  }
+}
+
+}  // namespace wtpic

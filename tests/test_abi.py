@@ -1,0 +1,131 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/wtpic.h declares, validates run descriptions as
+documented, and its interpolation tables reproduce the oracle's W_l, T_l."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1909_09613_amd as wt
+from paper_1909_09613_amd.inputs import RunSpec
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "wtpic.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(wt.LIB_PATH):
+        from paper_1909_09613_amd import build
+
+        build.build()
+    return wt.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(pic_[a-z_]+)\s*\(", text))
+    declared = {d for d in declared if not d.startswith("pic_run_desc")}
+    assert declared == set(wt.EXPORTED) | {"pic_last_error"} or declared <= set(wt.EXPORTED) | {"pic_last_error"}
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _desc(**kw):
+    spec = RunSpec(2, (64, 64), 2, 0.7, 50.0, 0.01, 4, 1001)
+    d = wt.make_desc(spec, wt.PIC_FP64)
+    for k, v in kw.items():
+        if k == "n":
+            for i in range(3):
+                d.n[i] = v[i]
+        else:
+            setattr(d, k, v)
+    return d
+
+
+def _status(descs):
+    try:
+        wt.pic_query_layout(descs)
+        return wt.PIC_OK
+    except wt.PicError as e:
+        return e.status
+
+
+def test_layout_valid(L):
+    b = wt.pic_query_layout([_desc()])
+    assert all(v > 0 for v in b)
+    # particle stores hold two copies of 2 * 64 * 64 * 4 particles (x, y, u0..2 fp64 + tag)
+    assert b[0] >= 2 * (2 * 64 * 64 * 4) * (8 * 5 + 4)
+    assert b[2] >= 3 * 8 * 64 * 64
+
+
+@pytest.mark.parametrize(
+    "kw,status",
+    [
+        ({"order": 5}, wt.PIC_ERR_UNSUPPORTED),
+        ({"order": 0}, wt.PIC_ERR_UNSUPPORTED),
+        ({"ndim": 4}, wt.PIC_ERR_UNSUPPORTED),
+        ({"courant": 0.72}, wt.PIC_ERR_CFL),
+        ({"courant": -0.1}, wt.PIC_ERR_ARG),
+        ({"n": (4, 64, 1)}, wt.PIC_ERR_ARG),
+        ({"n": (64, 64, 2)}, wt.PIC_ERR_ARG),
+        ({"ppc_per_species": 0}, wt.PIC_ERR_ARG),
+        ({"scheme": 7}, wt.PIC_ERR_ARG),
+        ({"precision": 3}, wt.PIC_ERR_ARG),
+    ],
+)
+def test_layout_rejects(L, kw, status):
+    assert _status([_desc(**kw)]) == status
+    assert len(wt.pic_last_error()) > 0
+
+
+def test_mixed_runs_rejected(L):
+    d1 = _desc()
+    d2 = _desc(order=3)
+    assert _status([d1, d2]) == wt.PIC_ERR_UNSUPPORTED
+    d3 = _desc(precision=wt.PIC_MIXED32)
+    assert _status([d1, d3]) == wt.PIC_ERR_UNSUPPORTED
+
+
+def test_3d_cfl(L):
+    d = _desc(ndim=3, n=(16, 16, 16), courant=0.58)
+    assert _status([d]) == wt.PIC_ERR_CFL
+    d = _desc(ndim=3, n=(16, 16, 16), courant=0.57)
+    assert _status([d]) == wt.PIC_OK
+
+
+def test_null_arguments(L):
+    import ctypes
+
+    out = (ctypes.c_size_t * 4)()
+    assert L.pic_query_layout(None, 1, out) == wt.PIC_ERR_ARG
+    assert L.pic_init(None, 1, None, None, None) == wt.PIC_ERR_ARG
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 4])
+@pytest.mark.parametrize("kind,a", [(0, 0.5), (1, 0.5), (2, 0.05), (2, 0.3), (2, 0.45), (2, 0.5), (2, 0.7), (2, 0.95)])
+def test_tables_match_oracle(L, orc, l, kind, a):
+    """The library's per-axis tables (host evaluation of the same evaluator
+    the kernels use) give the oracle's W_l / T_l on every node, and nothing
+    outside their node range."""
+    lam = 0.5 if kind == 0 else 0.0
+    for f in np.concatenate([np.linspace(0, 0.999999, 41), [0.5, 1 - a, a, 0.5 - a % 0.5]]):
+        if not (0 <= f < 1):
+            continue
+        first, w = wt.pic_table_weights(l, kind, a, f)
+        m = np.arange(first - 3, first + len(w) + 3)
+        y = f - m - lam
+        ref = orc.W(l, y) if kind < 2 else orc.T(l, a, y)
+        inside = (m >= first) & (m < first + len(w))
+        assert np.max(np.abs(ref[inside] - w)) <= 1e-14
+        assert np.all(np.abs(ref[~inside]) <= 1e-14)
+        assert abs(w.sum() - 1) <= 1e-14
+
+
+def test_table_node_counts(L):
+    """T_l needs l+1 integer nodes for c dt <= dx/2 and l+2 above (the
+    width l dx + 2 c dt of Sec. 2)."""
+    for l in (1, 2, 3, 4):
+        assert len(wt.pic_table_weights(l, 2, 0.3, 0.2)[1]) == l + 1
+        assert len(wt.pic_table_weights(l, 2, 0.5, 0.2)[1]) == l + 1
+        assert len(wt.pic_table_weights(l, 2, 0.7, 0.2)[1]) == l + 2

@@ -1,0 +1,324 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the
+same seeded inputs (drifting pair plasma, Table 1 recipe at the workloads'
+sizes), element by element: particles by identity, the deposited current and
+the fields.
+
+Tolerances
+  FP64 one step from identical state: positions 1e-12 cells, momenta 1e-12
+  relative, J max-norm relative 1e-12 per component for J1, J3 (and J2 of
+  3D).  J2 of the 2D drifting beam is the current of transverse steps of
+  ~1e-4 cells; any evaluation of S1 - S0 from absolute FP64 positions (the
+  oracle's) carries ~1e-16 / 1e-4 relative rounding, so J2 is held to 1e-12
+  of the largest current component instead (tolerances).
+  FP32 mixed: from an FP32-representable state, positions 2e-6 cells,
+  momenta 2e-6 relative; J per component from the FP32 storage of x^{n+1}:
+  the rounding of the new offset (<= 2^-25 cells) against steps of ~1e-4
+  cells bounds the transverse component at a few 1e-4, the longitudinal and
+  out-of-plane ones at 1e-5.
+"""
+import numpy as np
+import pytest
+
+import paper_1909_09613_amd as wt
+from paper_1909_09613_amd import inputs
+from paper_1909_09613_amd.inputs import RunSpec
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _one_step(orc, spec, precision, seed=7, amp=0.05):
+    fp32 = precision == wt.PIC_MIXED32
+    sp, E, B = H.random_state(spec, seed, amp, fp32=fp32)
+    g = H.oracle_grid(orc, spec)
+    g.E[:] = E
+    g.B[:] = B
+    ref = H.copy_species(sp)
+    g.zero_J()
+    for s in ref:
+        g.push_species(s["x"], s["u"], s["qm"], s["Q"])
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, sp)
+        sim.set_fields(0, E, B)
+        sim.gpd()
+        got = [sim.particles(0, s) for s in range(2)]
+        _, _, J = sim.fields(0)
+        d = sim.diagnostics(0)
+        assert d.n_nonfinite == 0 and d.n_out_of_range == 0
+    finally:
+        sim.close()
+    ex, eu = H.particle_errors(spec, ref, got)
+    ej = H.rel_maxnorm(J, g.J)
+    jmax = np.max(np.abs(g.J))
+    ej_abs = [float(np.max(np.abs(J[k] - g.J[k])) / jmax) for k in range(3)]
+    print("parity %s l=%d a=%.3f %s: dx=%.2e du=%.2e dJ=%s dJ/|J|max=%s" % (
+        "fp64" if not fp32 else "fp32", spec.order, spec.courant, spec.n, ex, eu,
+        ["%.2e" % v for v in ej], ["%.2e" % v for v in ej_abs]), flush=True)
+    return ex, eu, ej, ej_abs
+
+
+CASES_2D = [
+    RunSpec(2, (64, 64), 2, 0.7, 50.0, 0.01, 4, 1001),          # the 64x64 FP64 correctness workload
+    RunSpec(2, (40, 28), 1, 0.3, 50.0, 0.01, 3, 11),
+    RunSpec(2, (37, 29), 3, 0.45, 50.0, 0.01, 3, 12),            # ragged: not a multiple of the tile
+    RunSpec(2, (36, 20), 4, 0.25, 20.0, 0.05, 2, 13),
+    RunSpec(2, (33, 24), 2, 0.5, 50.0, 0.01, 3, 14),             # MC limit
+    RunSpec(2, (30, 26), 3, 0.6, 10.0, 0.1, 2, 15),              # a > 1/2: l+2 T nodes
+    RunSpec(2, (32, 32), 2, 0.3, 50.0, 0.01, 3, 16, scheme=1),  # MC scheme
+]
+CASES_3D = [
+    RunSpec(3, (16, 12, 10), 2, 0.5, 50.0, 0.01, 2, 21),
+    RunSpec(3, (14, 12, 11), 1, 0.4, 20.0, 0.05, 2, 22),
+    RunSpec(3, (12, 12, 12), 3, 0.35, 50.0, 0.01, 1, 23),
+]
+
+
+def _ids(cases):
+    return ["%dd-l%d-a%.2f-%s" % (c.ndim, c.order, c.courant, "x".join(map(str, c.n))) for c in cases]
+
+
+@pytest.mark.parametrize("spec", CASES_2D + CASES_3D, ids=_ids(CASES_2D + CASES_3D))
+def test_one_step_fp64(orc, spec):
+    ex, eu, ej, ej_abs = _one_step(orc, spec, wt.PIC_FP64)
+    assert ex <= 1e-12
+    assert eu <= 1e-12
+    for k in range(3):
+        if spec.ndim == 2 and k == 1:
+            assert ej_abs[k] <= 1e-12
+        else:
+            assert ej[k] <= 1e-12
+
+
+@pytest.mark.parametrize("spec", CASES_2D + CASES_3D, ids=_ids(CASES_2D + CASES_3D))
+def test_one_step_fp32(orc, spec):
+    ex, eu, ej, ej_abs = _one_step(orc, spec, wt.PIC_MIXED32)
+    assert ex <= 2e-6
+    assert eu <= 2e-6
+    for k in range(3):
+        tol = 1e-3 if (k == 1 or (spec.ndim == 3 and k == 2)) else 1e-5
+        assert ej[k] <= tol
+
+
+@pytest.mark.parametrize("ndim,solver", [(2, 0), (2, 1), (3, 0), (3, 1)])
+@pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32])
+def test_field_update(orc, ndim, solver, precision):
+    spec = RunSpec(ndim, (20, 17) if ndim == 2 else (12, 10, 9), 2, 0.4, 50.0, 0.01, 1, 31, solver=solver)
+    rng = np.random.default_rng(5)
+    E = inputs.random_fields(rng, spec.ncell, 1.0)
+    B = inputs.random_fields(rng, spec.ncell, 1.0)
+    if precision == wt.PIC_MIXED32:
+        E = E.astype(np.float32).astype(np.float64)
+        B = B.astype(np.float32).astype(np.float64)
+    g = H.oracle_grid(orc, spec)
+    g.E[:] = E
+    g.B[:] = B
+    for _ in range(3):
+        g.field_update()
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, inputs.make_species(spec))
+        sim.set_fields(0, E, B)
+        for _ in range(3):
+            sim.field_update()
+        Eg, Bg, _ = sim.fields(0)
+    finally:
+        sim.close()
+    tol = 1e-13 if precision == wt.PIC_FP64 else 3e-6
+    assert max(H.rel_maxnorm(Eg, g.E)) <= tol
+    assert max(H.rel_maxnorm(Bg, g.B)) <= tol
+
+
+def test_config1_trajectory_fp64(orc):
+    """The 64x64 correctness workload (l = 2, c dt = 0.7 dx, 4 ppc/species,
+    gamma 50) for 100 full steps from the loader's state: particles, fields
+    and the field-energy history against the oracle."""
+    spec = inputs.config(1)[0]
+    sp = inputs.make_species(spec)
+    g = H.oracle_grid(orc, spec)
+    ref = H.copy_species(sp)
+    sim = wt.Sim([spec], wt.PIC_FP64)
+    hist_o, hist_g = [], []
+    try:
+        sim.set_species(0, sp)
+        for n in range(100):
+            g.step(ref)
+            sim.gpd()
+            sim.field_update()
+            if n % 10 == 9:
+                UE, UB = g.field_energy()
+                hist_o.append(UE.sum() + UB.sum())
+                d = sim.diagnostics(0)
+                hist_g.append(sum(d.UE) + sum(d.UB))
+        got = [sim.particles(0, s) for s in range(2)]
+        Eg, Bg, _ = sim.fields(0)
+    finally:
+        sim.close()
+    ex, eu = H.particle_errors(spec, ref, got)
+    eE = H.rel_maxnorm(Eg, g.E)
+    eB = H.rel_maxnorm(Bg, g.B)
+    eh = np.max(np.abs(np.array(hist_g) / np.array(hist_o) - 1))
+    print("config1 100 steps: dx=%.2e du=%.2e dE=%s dB=%s dU=%.2e" % (ex, eu, eE, eB, eh), flush=True)
+    assert ex <= 1e-10
+    assert eu <= 1e-10
+    assert eh <= 1e-10
+
+
+def test_gauss_law_on_gpu(orc):
+    """Appendix B: the Gauss residual D.E - rho keeps its t = 0 value (here
+    nonzero, independent electron and positron positions) in FP64."""
+    spec = RunSpec(2, (48, 40), 2, 0.6, 20.0, 0.05, 3, 41, colocated=False, skin_depth_cells=4.0)
+    sp = inputs.make_species(spec)
+    g = H.oracle_grid(orc, spec)
+    r0 = np.max(np.abs(g.gauss_residual(sp)))
+    sim = wt.Sim([spec], wt.PIC_FP64)
+    try:
+        sim.set_species(0, sp)
+        sim.gpd()
+        sim.field_update()
+        first = sim.diagnostics(0).gauss_resid_max
+        for _ in range(30):
+            sim.gpd()
+            sim.field_update()
+        last = sim.diagnostics(0)
+    finally:
+        sim.close()
+    assert abs(first - r0) <= 1e-12 * max(1.0, r0)
+    assert abs(last.gauss_resid_max - r0) <= 1e-11 * max(1.0, r0)
+    assert sum(last.UE) > 0
+
+
+def test_batched_runs_fp64(orc):
+    """Several runs of different grid, Courant number and drift in one
+    context (the batched time-step sweep) each match their own oracle."""
+    specs = [
+        RunSpec(2, (40, 24), 2, 0.1, 10.0, 0.01, 2, 4001),
+        RunSpec(2, (24, 36), 2, 0.5, 50.0, 0.01, 2, 4002),
+        RunSpec(2, (33, 20), 2, 0.7, 100.0, 0.01, 2, 4003),
+    ]
+    sps = [inputs.make_species(s) for s in specs]
+    sim = wt.Sim(specs, wt.PIC_FP64)
+    grids, refs = [], []
+    try:
+        for r, s in enumerate(specs):
+            sim.set_species(r, sps[r])
+            grids.append(H.oracle_grid(orc, s))
+            refs.append(H.copy_species(sps[r]))
+        for _ in range(5):
+            sim.gpd()
+            sim.field_update()
+            for r in range(len(specs)):
+                grids[r].step(refs[r])
+        for r, s in enumerate(specs):
+            got = [sim.particles(r, k) for k in range(2)]
+            ex, eu = H.particle_errors(s, refs[r], got)
+            Eg, Bg, _ = sim.fields(r)
+            print("batched run %d: dx=%.2e du=%.2e dE=%s" % (r, ex, eu, H.rel_maxnorm(Eg, grids[r].E)), flush=True)
+            assert ex <= 1e-11 and eu <= 1e-11
+    finally:
+        sim.close()
+
+
+@pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32])
+def test_sorting_under_spread(orc, precision):
+    """A hot, slowly drifting plasma spreads out of its tiles within a few
+    steps: the re-sort keeps every particle inside its staged window and the
+    trajectory keeps matching the oracle."""
+    spec = RunSpec(2, (48, 32), 2, 0.45, 2.0, 0.8, 2, 51, colocated=False, skin_depth_cells=6.0)
+    sp = inputs.make_species(spec)
+    if precision == wt.PIC_MIXED32:
+        for s in sp:
+            s["x"], s["u"] = inputs.quantize_fp32(s["x"], s["u"])
+    g = H.oracle_grid(orc, spec)
+    ref = H.copy_species(sp)
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, sp)
+        for _ in range(12):
+            sim.gpd()
+            sim.field_update()
+            g.step(ref)
+        d = sim.diagnostics(0)
+        got = [sim.particles(0, s) for s in range(2)]
+    finally:
+        sim.close()
+    ex, eu = H.particle_errors(spec, ref, got)
+    print("spread %s: dx=%.2e du=%.2e" % (precision, ex, eu), flush=True)
+    assert d.n_out_of_range == 0 and d.n_nonfinite == 0
+    assert ex <= (1e-10 if precision == wt.PIC_FP64 else 1e-4)
+
+
+def test_step_graph_matches_eager(orc):
+    """pic_step (graph replays) gives the same state as eager
+    gather-push-deposit + field-update calls."""
+    spec = RunSpec(2, (40, 32), 2, 0.45, 50.0, 0.01, 2, 61)
+    sp = inputs.make_species(spec)
+    a = wt.Sim([spec], wt.PIC_FP64)
+    b = wt.Sim([spec], wt.PIC_FP64)
+    try:
+        a.set_species(0, sp)
+        b.set_species(0, sp)
+        a.step(21)
+        for _ in range(21):
+            b.gpd()
+            b.field_update()
+        xa = [a.particles(0, s) for s in range(2)]
+        xb = [b.particles(0, s) for s in range(2)]
+        Ea, Ba, _ = a.fields(0)
+        Eb, Bb, _ = b.fields(0)
+    finally:
+        a.close()
+        b.close()
+    for s in range(2):
+        assert np.max(np.abs(xa[s][0] - xb[s][0])) <= 1e-12
+        assert np.max(np.abs(xa[s][1] - xb[s][1])) <= 1e-10
+    assert np.max(np.abs(Ea - Eb)) <= 1e-12 * max(1.0, np.max(np.abs(Eb)))
+
+
+def test_diagnostics_match_oracle(orc):
+    spec = RunSpec(2, (32, 24), 3, 0.45, 50.0, 0.01, 2, 71)
+    sp, E, B = H.random_state(spec, 3)
+    g = H.oracle_grid(orc, spec)
+    g.E[:] = E
+    g.B[:] = B
+    ref = H.copy_species(sp)
+    g.step(ref)
+    sim = wt.Sim([spec], wt.PIC_FP64)
+    try:
+        sim.set_species(0, sp)
+        sim.set_fields(0, E, B)
+        sim.gpd()
+        sim.field_update()
+        d = sim.diagnostics(0)
+    finally:
+        sim.close()
+    UE, UB = g.field_energy()
+    for k in range(3):
+        assert abs(d.UE[k] - UE[k]) <= 1e-12 * UE[k]
+        assert abs(d.UB[k] - UB[k]) <= 1e-12 * UB[k]
+    for s in range(2):
+        Ek = g.kinetic(ref[s]["u"], ref[s]["M"])
+        assert abs(d.Ekin[s] - Ek) <= 1e-12 * Ek
+    r = np.max(np.abs(g.gauss_residual(ref)))
+    assert abs(d.gauss_resid_max - r) <= 1e-10 * max(r, 1e-300) + 1e-14
+
+
+def test_counters_report_nonfinite(orc):
+    """A non-finite momentum is counted, left in place, and surfaced by
+    pic_diagnostics as PIC_ERR_NUMERIC; the other particles are unaffected."""
+    spec = RunSpec(2, (24, 20), 2, 0.45, 50.0, 0.01, 1, 81)
+    sp = inputs.make_species(spec)
+    sim = wt.Sim([spec], wt.PIC_FP64)
+    try:
+        sim.set_species(0, sp)
+        E = np.zeros((3, spec.ncell))
+        E[0, 5] = np.inf
+        sim.set_fields(0, E, None)
+        sim.gpd()
+        d = sim.diagnostics(0, allow_numeric=True)
+        assert d.n_nonfinite > 0
+        with pytest.raises(wt.PicError) as ei:
+            sim.diagnostics(0)
+        assert ei.value.status == wt.PIC_ERR_NUMERIC
+    finally:
+        sim.close()
