@@ -1,0 +1,209 @@
+"""Throughput of the WT gather + push + deposit step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed32|fp64]
+
+Workload: 2D periodic 1024 x 512 Yee grid, electron-positron pair plasma
+drifting along +x1 with gamma 50, thermal spread u_th = 0.01, 16 particles per
+cell per species (16.8M particles), cubic B-spline (l = 3), WT interpolation
+at c dt = 0.45 dx, synthetic seeded inputs (the paper's Table 1 recipe at
+this size).  A step is one full PIC step: re-sort check, gather + Boris +
+Esirkepov deposit (one kernel), Yee field update.
+
+Prints one JSON line.  `value` is particle-steps per second of the whole job
+over the K timed steps (inputs resident in HBM).  `roofline` refers to the
+dominant kernel, the gather-push-deposit kernel: its average launch time is
+measured with HIP events recorded by the library on the context stream around
+every launch of the timed region, and `achieved` is its algorithmic bytes per
+launch (particle state read and written once, E and B read and J written once
+per cell) over that time.  `traffic` is the HBM traffic per launch from the
+rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded under profiles/ for the
+current kernel source, else null.  `cpu_baseline` is the FP64 CPU oracle
+timed on a bounded sample of the same workload on one host core.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def particle_bytes(ndim, precision):
+    """Bytes of one particle read + written per step."""
+    if precision == "fp64":
+        return 2 * (8 * ndim + 24)
+    return 2 * (4 + 4 * ndim + 12)
+
+
+def cell_bytes(precision):
+    """Bytes per cell per step: E, B read once, FP64 J written once."""
+    rs = 8 if precision == "fp64" else 4
+    return 6 * rs + 3 * 8
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for name in ("gpd.hip", "common.hpp", "tables.hpp"):
+        with open(os.path.join(ROOT, "paper_1909_09613_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(precision, digest):
+    path = os.path.join(ROOT, "profiles", "gpd_traffic_1024x512_l3.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get(precision)
+    if not ent or ent.get("source_digest") != digest:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, species, E, B, budget_s=10.0):
+    """FP64 oracle (one core) on a bounded sample: the particles of the first
+    rows of the grid, pushed for one step at a time until budget_s elapses."""
+    from oracle import oracle as orc
+
+    g = orc.Grid(spec.ndim, spec.n, spec.order, spec.dt)
+    g.E[:] = E
+    g.B[:] = B
+    nsample = 65536
+    xs = [np.ascontiguousarray(s["x"][:nsample]) for s in species]
+    us = [np.ascontiguousarray(s["u"][:nsample]) for s in species]
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        g.zero_J()
+        for s, x, u in zip(species, xs, us):
+            g.push_species(x, u, s["qm"], s["Q"])
+            done += len(x)
+    dt = time.perf_counter() - t0
+    return {
+        "value": done / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+        "sample": "%d particles per species from the first grid rows, %d particle-steps of "
+                  "gather+push+deposit (no field update) in %.1f s" % (nsample, done, dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--precision", default="mixed32", choices=["mixed32", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--tile", default=None, help="tile shape, e.g. 32x16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1909_09613_amd as wt
+    from paper_1909_09613_amd import inputs
+
+    spec = inputs.config(2)[0]
+    prec = wt.PIC_FP64 if args.precision == "fp64" else wt.PIC_MIXED32
+    t_setup = time.perf_counter()
+    species = inputs.make_species(spec)
+    sim = wt.Sim([spec], prec)
+    if args.tile:
+        t = [int(v) for v in args.tile.split("x")] + [0]
+        wt.pic_set_tiling(sim.ctx, tuple(t[:3]), 0, 0)
+    sim.set_species(0, species)
+    np_total = 2 * spec.ncell * spec.ppc_s
+    print("setup %.1f s, %d particles" % (time.perf_counter() - t_setup, np_total), file=sys.stderr, flush=True)
+
+    # warmup: graph replays (includes the first sort)
+    sim.step(args.warmup)
+    sim.synchronize()
+
+    # timed region: eager steps with the library's per-launch kernel events
+    wt.pic_kernel_timing(sim.ctx, True)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(sim.stream):
+        start.record(sim.stream)
+        for _ in range(args.steps):
+            sim.gpd()
+            sim.field_update()
+        stop.record(sim.stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(stop)
+    gpd_ms, launches = wt.pic_kernel_timing(sim.ctx, False)
+
+    # the same number of steps replayed from the captured graph
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sim.stream):
+        start.record(sim.stream)
+        sim.step(args.steps)
+        stop.record(sim.stream)
+    stop.synchronize()
+    ms_graph = start.elapsed_time(stop)
+
+    d = sim.diagnostics(0)
+    sim.close()
+
+    ms_step = ms_total / args.steps
+    value = np_total * args.steps / (ms_total / 1e3)
+    prec_name = args.precision
+    alg_bytes = np_total * particle_bytes(spec.ndim, prec_name) + spec.ncell * cell_bytes(prec_name)
+    achieved = alg_bytes / (gpd_ms / 1e3) / 1e9
+    digest = source_digest()
+    traffic = load_traffic(prec_name, digest)
+
+    if not args.no_cpu:
+        rng = np.random.default_rng(0)
+        E = inputs.random_fields(rng, spec.ncell, 1e-3)
+        B = inputs.random_fields(rng, spec.ncell, 1e-3)
+        cpu = cpu_baseline(spec, inputs.make_species(spec), E, B)
+    else:
+        cpu = None
+
+    out = {
+        "metric": "particle-steps/sec (gather+push+deposit) on 1 MI355X; % HBM roofline; FP32 vs FP64",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec_name == "mixed32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D periodic 1024x512, drifting pair plasma gamma 50, u_th 0.01, 16 ppc/species, "
+                        "cubic B-spline, WT at c dt = 0.45 dx",
+            "particles": np_total, "precision": prec_name,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "gpd_kernel", "kernel_ms": gpd_ms, "launches": launches,
+            "algorithmic_bytes_per_launch": alg_bytes, "source_digest": digest,
+        },
+        "graph_ms_per_step": ms_graph / args.steps,
+        "cpu_baseline": cpu,
+        "check": {"n_nonfinite": d.n_nonfinite, "n_out_of_range": d.n_out_of_range, "n_sorts": d.n_sorts,
+                  "field_energy": sum(d.UE) + sum(d.UB)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

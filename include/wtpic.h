@@ -103,6 +103,7 @@ typedef struct {
   double gauss_resid_max;/* max |D.E - rho| on integer nodes (Appendix B, Eq. gauss) */
   int64_t n_nonfinite;   /* particles with a non-finite momentum or position */
   int64_t n_out_of_range;/* particles found outside their tile's staged window */
+  int64_t n_sorts;       /* counting sorts performed so far (all runs) */
 } pic_diag;
 
 typedef struct pic_ctx pic_ctx;

@@ -56,7 +56,7 @@ class pic_diag(ctypes.Structure):
         ("step", ctypes.c_int64), ("time", ctypes.c_double), ("UE", ctypes.c_double * 3),
         ("UB", ctypes.c_double * 3), ("Ekin", ctypes.c_double * 2), ("momentum", ctypes.c_double * 3),
         ("gauss_resid_max", ctypes.c_double), ("n_nonfinite", ctypes.c_int64),
-        ("n_out_of_range", ctypes.c_int64),
+        ("n_out_of_range", ctypes.c_int64), ("n_sorts", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -64,7 +64,7 @@ class pic_diag(ctypes.Structure):
             "step": self.step, "time": self.time, "UE": list(self.UE), "UB": list(self.UB),
             "Ekin": list(self.Ekin), "momentum": list(self.momentum),
             "gauss_resid_max": self.gauss_resid_max, "n_nonfinite": self.n_nonfinite,
-            "n_out_of_range": self.n_out_of_range,
+            "n_out_of_range": self.n_out_of_range, "n_sorts": self.n_sorts,
         }
 
 

@@ -73,15 +73,19 @@ __device__ __forceinline__ bool finite3(Real a, Real b, Real c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// LDS atomic add that skips exact zeros (stencil slots a particle does not
+// reach); masked lanes cost the LDS nothing.
 template <class Acc>
 __device__ __forceinline__ void lds_add(Acc* p, Acc v) {
-  atomicAdd(p, v);
+  if (v != Acc(0)) atomicAdd(p, v);
 }
 
 }  // namespace
 
 template <class P, int L, int DIM, int KT>
-__device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, const int g,
+__device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
+                                         const RunDev<typename P::Real>* __restrict__ runs,
+                                         const int* __restrict__ tile_run, const int g,
                                          unsigned char* lds, int* sred) {
   using Real = typename P::Real;
   using Acc = typename P::Acc;
@@ -91,8 +95,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
 
-  const int r = A.tile_run[g];
-  const RunDev<Real>& R = A.runs[r];
+  const int r = tile_run[g];
+  const RunDev<Real>& R = runs[r];
   const int lt = g - R.tile0;
   int org[3];
   org[0] = (lt % R.ntile[0]) * A.tile[0];
@@ -209,10 +213,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
     bool inwin = true;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+      // periodic image nearest the box: rel in [lo, lo + n), the box centred
+      // in that range (a box as wide as the axis starts it)
       const int n = R.n[d];
-      int rr = c[d] - org[d];
-      if (rr >= (n + 1) / 2) rr -= n;
-      else if (rr < -(n / 2)) rr += n;
+      const int slack = max(0, n - 1 - (bb[2 * d + 1] - bb[2 * d]));
+      const int lo = bb[2 * d] - (slack >> 1);
+      int rr = wrapi(c[d] - org[d] - lo, n) + lo;
       rel[d] = rr;
       inwin = inwin && (rr + R.glo[d] >= fo[d]) && (rr + R.ghi[d] < fo[d] + fs[d]) &&
               (rr + R.dlo[d] >= jo[d]) && (rr + R.dhi[d] < jo[d] + jsz[d]);
@@ -352,6 +358,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
     // ---- form factors and their differences on the union stencil -----------
     Real S0u[3][NU], DSu[3][NU];
     int iu[3] = {0, 0, 0};
+    bool cross[3] = {false, false, false};  // union stencil one node wider than S0
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const Tab<Real>& Tw = R.Wi[d];
@@ -362,6 +369,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
       Real s0[NW], dA[NW], dB[NW];
       tab_eval<L, NW, false>(Tw, g0, s0);
       const int db = b1 - b0;
+      cross[d] = db != 0;
       const Real eA = (db == 0) ? g1 : (db > 0 ? Real(1) : Real(0));
       const Real lA = (db == 0) ? dd[d] : (db > 0 ? Real(1) - g0 : -g0);
       tab_diff<L>(Tw, g0, eA, lA, dA);
@@ -399,7 +407,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
 #pragma unroll
         for (int u = 0; u <= L; ++u) {
           acc += DSu[0][u] * fy;
-          lds_add<Acc>(row + u, Acc(jx * acc));
+          // the prefix over all of S0's nodes is zero unless the stencil widened
+          if (u < L || cross[0]) lds_add<Acc>(row + u, Acc(jx * acc));
         }
       }
 #pragma unroll
@@ -410,7 +419,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
 #pragma unroll
         for (int v = 0; v <= L; ++v) {
           acc += DSu[1][v] * fx;
-          lds_add<Acc>(col + jwx * v, Acc(jy * acc));
+          if (v < L || cross[1]) lds_add<Acc>(col + jwx * v, Acc(jy * acc));
         }
       }
       const Real vz = jz * vv[2];
@@ -435,7 +444,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
 #pragma unroll
           for (int u = 0; u <= L; ++u) {
             acc += DSu[0][u] * tr;
-            lds_add<Acc>(row + u, Acc(jx * acc));
+            if (u < L || cross[0]) lds_add<Acc>(row + u, Acc(jx * acc));
           }
         }
       }
@@ -451,7 +460,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
 #pragma unroll
           for (int v = 0; v <= L; ++v) {
             acc += DSu[1][v] * tr;
-            lds_add<Acc>(col + jwx * v, Acc(jy * acc));
+            if (v < L || cross[1]) lds_add<Acc>(col + jwx * v, Acc(jy * acc));
           }
         }
       }
@@ -467,7 +476,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
 #pragma unroll
           for (int w = 0; w <= L; ++w) {
             acc += DSu[2][w] * tr;
-            lds_add<Acc>(col + jwx * jwy * w, Acc(jz * acc));
+            if (w < L || cross[2]) lds_add<Acc>(col + jwx * jwy * w, Acc(jz * acc));
           }
         }
       }
@@ -557,6 +566,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
           hi = min(A.tile[d], R.n[d] - org[d]) - 1;
         }
         need = need || (hi - lo > A.guard[d]);
+        // a box that drifted a whole period keeps canonical coordinates
+        const int mid = (lo + hi) >> 1;
+        const int shift = R.n[d] * (mid >= 0 ? mid / R.n[d] : -((R.n[d] - 1 - mid) / R.n[d]));
+        lo -= shift;
+        hi -= shift;
       }
       A.bbox[g * 6 + 2 * d] = lo;
       A.bbox[g * 6 + 2 * d + 1] = hi;
@@ -568,7 +582,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A, con
 }
 
 template <class P, int L, int DIM>
-__global__ void __launch_bounds__(256) gpd_kernel(GpdArgs<typename P::Real> A) {
+__global__ void __launch_bounds__(256)
+    gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
+               const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
   __shared__ int sred[8];
   // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
@@ -577,17 +593,17 @@ __global__ void __launch_bounds__(256) gpd_kernel(GpdArgs<typename P::Real> A) {
   const int per = gridDim.x >> 3;
   const int g = (b & 7) * per + (b >> 3);
   if (g >= A.G) return;
-  const int kt = A.runs[A.tile_run[g]].KT;
+  const int kt = runs[tile_run[g]].KT;
   if (kt == L + 1)
-    gpd_tile<P, L, DIM, L + 1>(A, g, lds_dyn, sred);
+    gpd_tile<P, L, DIM, L + 1>(A, runs, tile_run, g, lds_dyn, sred);
   else
-    gpd_tile<P, L, DIM, L + 2>(A, g, lds_dyn, sred);
+    gpd_tile<P, L, DIM, L + 2>(A, runs, tile_run, g, lds_dyn, sred);
 }
 
 template <class P, int L, int DIM>
 static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
   const int grid = ((a.G + 7) / 8) * 8;
-  hipLaunchKernelGGL((gpd_kernel<P, L, DIM>), dim3(grid), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((gpd_kernel<P, L, DIM>), dim3(grid), dim3(256), lds, s, a, a.runs, a.tile_run);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
-constexpr int kMinTile = 4;        // smallest tile edge; bounds the scratch layout
+// smallest tile edge; bounds the scratch layout
+int min_tile(int ndim) { return ndim == 2 ? 4 : 2; }
 constexpr int kMaxLds = 64 * 1024; // per-workgroup LDS budget of the particle kernel
 constexpr size_t kAlign = 256;
 
@@ -121,7 +122,7 @@ Layout make_layout(const pic_run_desc* runs, int n_runs) {
     long long c = 1, g = 1;
     for (int k = 0; k < ndim; ++k) {
       c *= runs[r].n[k];
-      g *= ceil_div(runs[r].n[k], kMinTile);
+      g *= ceil_div(runs[r].n[k], min_tile(ndim));
     }
     np += 2 * c * runs[r].ppc_per_species;
     nc += c;
@@ -190,6 +191,7 @@ struct pic_ctx {
   int margin = 3, sort_every = 2;
   int fw[3] = {1, 1, 1}, jw[3] = {1, 1, 1}, guard[3] = {0, 0, 0};
   size_t lds = 0;
+  size_t lds_budget = 64 * 1024;
   pic_buffers bufs{};
   Layout lay{};
   char* P = nullptr;
@@ -350,16 +352,20 @@ pic_status apply_tiling(pic_ctx* c) {
       c->guard[k] = 0;
       continue;
     }
+    // A step stages the box its particles had after the previous step.  A
+    // box may exceed the guard by 2 cells per step until the next sort
+    // opportunity (every sort_every steps), so a staged box spans at most
+    // guard + 2 (sort_every - 1) cells plus the stencil reach.
     c->guard[k] = c->tile[k] + 2 * (c->margin - c->sort_every) - 1;
-    c->fw[k] = c->guard[k] + 2 * c->sort_every + span_g[k] + 1;
-    c->jw[k] = c->guard[k] + 2 * c->sort_every + span_d[k] + 1;
+    c->fw[k] = c->guard[k] + 2 * (c->sort_every - 1) + span_g[k] + 1;
+    c->jw[k] = c->guard[k] + 2 * (c->sort_every - 1) + span_d[k] + 1;
     if (c->guard[k] < c->tile[k]) return c->fail(PIC_ERR_ARG, "margin must exceed sort_every");
   }
   const size_t fcap = (size_t)c->fw[0] * c->fw[1] * c->fw[2];
   const size_t jcap = (size_t)c->jw[0] * c->jw[1] * c->jw[2];
   const size_t rs = sizeof(Real);
-  c->lds = 6 * rs * fcap + 3 * rs * jcap;
-  if (c->lds > (size_t)kMaxLds) return c->fail(PIC_ERR_ARG, "tile and margin need more than 64 KiB of LDS");
+  c->lds = 6 * rs * fcap + 3 * sizeof(double) * jcap;
+  if (c->lds > (size_t)c->lds_budget) return c->fail(PIC_ERR_ARG, "tile and margin need more LDS than the workgroup budget");
   // device tables
   c->tile_run_host.assign(G, 0);
   for (int r = 0; r < c->nruns; ++r)
@@ -711,6 +717,7 @@ pic_status diag_t(pic_ctx* c, int run, pic_diag* out) {
   std::memcpy(&out->gauss_resid_max, &acc[11], sizeof(double));
   out->n_nonfinite = (int64_t)ds.n_nonfinite;
   out->n_out_of_range = (int64_t)ds.n_out_of_range;
+  out->n_sorts = (int64_t)ds.n_sorts;
   if (ds.n_nonfinite || ds.n_out_of_range) return c->fail(PIC_ERR_NUMERIC, "device counted non-finite or out-of-window particles");
   return PIC_OK;
 }
@@ -791,19 +798,27 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
   }
   c->ncell_total = cell0;
   c->np_total = p0;
-  // default tiling: as large as the LDS budget allows, at most 32 x 16 (2D) / 8 x 8 x 4 (3D)
-  if (c->ndim == 2) {
-    c->tile[0] = c->f64() ? 16 : 32;
-    c->tile[1] = 16;
-    c->tile[2] = 1;
-  } else {
-    c->tile[0] = 8;
-    c->tile[1] = 8;
-    c->tile[2] = c->f64() ? 2 : 4;
+  // default tiling: the first candidate whose LDS fits the budget.  2D
+  // re-sorts are checked every 2 steps with a 3-cell margin; 3D windows are
+  // costlier, so 3D checks every step with a 2-cell margin.
+  {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 0)
+      c->lds_budget = std::min<size_t>((size_t)lim, (size_t)kMaxLds);
   }
-  c->margin = 3;
-  c->sort_every = 2;
-  st = c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c);
+  static const int cand2[][3] = {{32, 16, 1}, {32, 8, 1}, {16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}};
+  static const int cand3[][3] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}};
+  const int ncand = (c->ndim == 2) ? 7 : 6;
+  c->margin = (c->ndim == 2) ? 3 : 2;
+  c->sort_every = (c->ndim == 2) ? 2 : 1;
+  st = PIC_ERR_ARG;
+  for (int i = 0; i < ncand && st != PIC_OK; ++i) {
+    const int* t = (c->ndim == 2) ? cand2[i] : cand3[i];
+    if (c->ndim == 2 && c->f64() && t[0] > 16) continue;
+    for (int k = 0; k < 3; ++k) c->tile[k] = t[k];
+    st = c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c);
+  }
   if (st == PIC_OK) st = c->f64() ? upload_static<double>(c) : upload_static<float>(c);
   if (st != PIC_OK) {
     g_err = c->err;
@@ -822,7 +837,7 @@ pic_status pic_set_tiling(pic_ctx* c, const int32_t tile[3], int32_t margin, int
   if (tile)
     for (int k = 0; k < c->ndim; ++k)
       if (tile[k] > 0) {
-        if (tile[k] < kMinTile) return c->fail(PIC_ERR_ARG, "tile edges must be >= 4");
+        if (tile[k] < min_tile(c->ndim)) return c->fail(PIC_ERR_ARG, "tile edges must be >= 4 (2D) or 2 (3D)");
         c->tile[k] = tile[k];
       }
   if (sort_every > 0) c->sort_every = sort_every;

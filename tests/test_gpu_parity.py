@@ -3,18 +3,23 @@ same seeded inputs (drifting pair plasma, Table 1 recipe at the workloads'
 sizes), element by element: particles by identity, the deposited current and
 the fields.
 
+Current metric.  Each J component is a sum of per-particle contributions of
+both signs (electrons and positrons drift together, so their J1 nearly
+cancels).  The error of component c is therefore measured against the scale
+of what was summed, max over nodes of |J_c(electrons)| + |J_c(positrons)|,
+not against the (possibly cancelled) total.
+
 Tolerances
-  FP64 one step from identical state: positions 1e-12 cells, momenta 1e-12
-  relative, J max-norm relative 1e-12 per component for J1, J3 (and J2 of
-  3D).  J2 of the 2D drifting beam is the current of transverse steps of
-  ~1e-4 cells; any evaluation of S1 - S0 from absolute FP64 positions (the
-  oracle's) carries ~1e-16 / 1e-4 relative rounding, so J2 is held to 1e-12
-  of the largest current component instead (tolerances).
-  FP32 mixed: from an FP32-representable state, positions 2e-6 cells,
-  momenta 2e-6 relative; J per component from the FP32 storage of x^{n+1}:
-  the rounding of the new offset (<= 2^-25 cells) against steps of ~1e-4
-  cells bounds the transverse component at a few 1e-4, the longitudinal and
-  out-of-plane ones at 1e-5.
+  FP64, one step from identical state: positions 1e-12 cells, momenta 1e-12
+  relative, J 1e-12 of the summed scale for the components along the drift
+  (J1) and out of the plane (J3 in 2D).  The transverse components (J2 in
+  2D, J2 and J3 in 3D) carry steps of only |d| ~ a u_th / gamma0 ~ 1e-4
+  cells, and the oracle forms S1 - S0 from FP64 values of order one, so its
+  own rounding is ~4e-16 / |d| ~ 5e-12 of the summed scale: 1e-11.
+  FP32 mixed, from an FP32-representable state: positions 2e-6 cells,
+  momenta 2e-6 relative; J1 (and J3 in 2D) 1e-5 of the summed scale;
+  transverse components 2e-4: the new offset is stored in FP32 (rounding
+  <= 2^-25 cells against steps of ~1e-4 cells).
 """
 import numpy as np
 import pytest
@@ -27,16 +32,26 @@ from tests import helpers as H
 pytestmark = pytest.mark.gpu
 
 
+def _oracle_current(orc, spec, sp, E, B):
+    """Oracle J of both species together and of each species alone."""
+    out = []
+    for which in (None, 0, 1):
+        g = H.oracle_grid(orc, spec)
+        g.E[:] = E
+        g.B[:] = B
+        ref = H.copy_species(sp)
+        g.zero_J()
+        for k, s in enumerate(ref):
+            if which is None or which == k:
+                g.push_species(s["x"], s["u"], s["qm"], s["Q"])
+        out.append((g, ref))
+    return out
+
+
 def _one_step(orc, spec, precision, seed=7, amp=0.05):
     fp32 = precision == wt.PIC_MIXED32
     sp, E, B = H.random_state(spec, seed, amp, fp32=fp32)
-    g = H.oracle_grid(orc, spec)
-    g.E[:] = E
-    g.B[:] = B
-    ref = H.copy_species(sp)
-    g.zero_J()
-    for s in ref:
-        g.push_species(s["x"], s["u"], s["qm"], s["Q"])
+    (g, ref), (ge, _), (gp, _) = _oracle_current(orc, spec, sp, E, B)
     sim = wt.Sim([spec], precision)
     try:
         sim.set_species(0, sp)
@@ -49,29 +64,33 @@ def _one_step(orc, spec, precision, seed=7, amp=0.05):
     finally:
         sim.close()
     ex, eu = H.particle_errors(spec, ref, got)
-    ej = H.rel_maxnorm(J, g.J)
-    jmax = np.max(np.abs(g.J))
-    ej_abs = [float(np.max(np.abs(J[k] - g.J[k])) / jmax) for k in range(3)]
-    print("parity %s l=%d a=%.3f %s: dx=%.2e du=%.2e dJ=%s dJ/|J|max=%s" % (
-        "fp64" if not fp32 else "fp32", spec.order, spec.courant, spec.n, ex, eu,
-        ["%.2e" % v for v in ej], ["%.2e" % v for v in ej_abs]), flush=True)
-    return ex, eu, ej, ej_abs
+    scale = np.max(np.abs(ge.J) + np.abs(gp.J), axis=1)
+    ej = [float(np.max(np.abs(J[k] - g.J[k])) / scale[k]) for k in range(3)]
+    print("parity %s %dD l=%d a=%.3f %s: dx=%.2e du=%.2e dJ/scale=%s" % (
+        "fp64" if not fp32 else "fp32", spec.ndim, spec.order, spec.courant, spec.n, ex, eu,
+        ["%.2e" % v for v in ej]), flush=True)
+    return ex, eu, ej
 
 
 CASES_2D = [
     RunSpec(2, (64, 64), 2, 0.7, 50.0, 0.01, 4, 1001),          # the 64x64 FP64 correctness workload
-    RunSpec(2, (40, 28), 1, 0.3, 50.0, 0.01, 3, 11),
+    RunSpec(2, (40, 28), 1, 0.3, 50.0, 0.01, 3, 11, colocated=False),
     RunSpec(2, (37, 29), 3, 0.45, 50.0, 0.01, 3, 12),            # ragged: not a multiple of the tile
-    RunSpec(2, (36, 20), 4, 0.25, 20.0, 0.05, 2, 13),
+    RunSpec(2, (36, 20), 4, 0.25, 20.0, 0.05, 2, 13, colocated=False),
     RunSpec(2, (33, 24), 2, 0.5, 50.0, 0.01, 3, 14),             # MC limit
     RunSpec(2, (30, 26), 3, 0.6, 10.0, 0.1, 2, 15),              # a > 1/2: l+2 T nodes
     RunSpec(2, (32, 32), 2, 0.3, 50.0, 0.01, 3, 16, scheme=1),  # MC scheme
 ]
 CASES_3D = [
     RunSpec(3, (16, 12, 10), 2, 0.5, 50.0, 0.01, 2, 21),
-    RunSpec(3, (14, 12, 11), 1, 0.4, 20.0, 0.05, 2, 22),
+    RunSpec(3, (14, 12, 11), 1, 0.4, 20.0, 0.05, 2, 22, colocated=False),
     RunSpec(3, (12, 12, 12), 3, 0.35, 50.0, 0.01, 1, 23),
 ]
+
+
+def _transverse(spec, k):
+    """Current components driven by the thermal (transverse) motion only."""
+    return k == 1 or (spec.ndim == 3 and k == 2)
 
 
 def _ids(cases):
@@ -80,24 +99,20 @@ def _ids(cases):
 
 @pytest.mark.parametrize("spec", CASES_2D + CASES_3D, ids=_ids(CASES_2D + CASES_3D))
 def test_one_step_fp64(orc, spec):
-    ex, eu, ej, ej_abs = _one_step(orc, spec, wt.PIC_FP64)
+    ex, eu, ej = _one_step(orc, spec, wt.PIC_FP64)
     assert ex <= 1e-12
     assert eu <= 1e-12
     for k in range(3):
-        if spec.ndim == 2 and k == 1:
-            assert ej_abs[k] <= 1e-12
-        else:
-            assert ej[k] <= 1e-12
+        assert ej[k] <= (1e-11 if _transverse(spec, k) else 1e-12)
 
 
 @pytest.mark.parametrize("spec", CASES_2D + CASES_3D, ids=_ids(CASES_2D + CASES_3D))
 def test_one_step_fp32(orc, spec):
-    ex, eu, ej, ej_abs = _one_step(orc, spec, wt.PIC_MIXED32)
+    ex, eu, ej = _one_step(orc, spec, wt.PIC_MIXED32)
     assert ex <= 2e-6
     assert eu <= 2e-6
     for k in range(3):
-        tol = 1e-3 if (k == 1 or (spec.ndim == 3 and k == 2)) else 1e-5
-        assert ej[k] <= tol
+        assert ej[k] <= (2e-4 if _transverse(spec, k) else 1e-5)
 
 
 @pytest.mark.parametrize("ndim,solver", [(2, 0), (2, 1), (3, 0), (3, 1)])
