@@ -87,7 +87,7 @@ struct DevState {
   int parity;                  // current particle store
   int sort_request;            // set when a tile's particles outgrew the staging margin
   int sort_active;             // the sort sequence in flight works
-  int pad;
+  int tile_queue;              // next tile for the persistent particle kernel
   unsigned long long n_nonfinite;
   unsigned long long n_out_of_range;
   unsigned long long n_sorts;
@@ -110,6 +110,7 @@ struct GpdArgs {
   int fw[3];             // field window capacity (nodes)
   int jw[3];             // current window capacity (nodes)
   int guard[3];          // bbox extent above which a re-sort is requested
+  int max_groups;        // workgroups launched (persistent, tile queue)
 };
 
 // Position of a (possibly negative or >= n) lattice index on a periodic axis.

@@ -73,14 +73,24 @@ __device__ __forceinline__ bool finite3(Real a, Real b, Real c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-// LDS atomic add that skips exact zeros (stencil slots a particle does not
-// reach); masked lanes cost the LDS nothing.
 template <class Acc>
 __device__ __forceinline__ void lds_add(Acc* p, Acc v) {
-  if (v != Acc(0)) atomicAdd(p, v);
+  atomicAdd(p, v);
 }
 
+// 1 / sqrt(x) and 1 / x: hardware approximations (1 ulp) for FP32, IEEE for FP64.
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
 }  // namespace
+
+// Workgroup size of the particle kernel: 2D tiles hold more particles.
+template <int DIM>
+constexpr int gpd_block() {
+  return DIM == 2 ? 512 : 256;
+}
 
 template <class P, int L, int DIM, int KT>
 __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
@@ -93,7 +103,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   constexpr int NW = L + 1;  // W nodes
   constexpr int NU = L + 2;  // union of old and new form-factor nodes
   const int tid = threadIdx.x;
-  const int nth = blockDim.x;
+  const int nth = gpd_block<DIM>();
 
   const int r = tile_run[g];
   const RunDev<Real>& R = runs[r];
@@ -291,9 +301,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     // ---- Boris -------------------------------------------------------------
     const Real eps = R.eps[sp];
     const Real umx = u0 + eps * E0, umy = u1 + eps * E1, umz = u2 + eps * E2;
-    const Real igm = Real(1) / sqrt(Real(1) + umx * umx + umy * umy + umz * umz);
+    const Real igm = fast_rsqrt(Real(1) + umx * umx + umy * umy + umz * umz);
     const Real tx = eps * B0 * igm, ty = eps * B1 * igm, tz = eps * B2 * igm;
-    const Real s2 = Real(2) / (Real(1) + tx * tx + ty * ty + tz * tz);
+    const Real s2 = Real(2) * fast_rcp(Real(1) + tx * tx + ty * ty + tz * tz);
     const Real sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
     const Real upx = umx + (umy * tz - umz * ty);
     const Real upy = umy + (umz * tx - umx * tz);
@@ -316,7 +326,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     u2 = n2;
 
     // ---- move ------------------------------------------------------------
-    const Real igam = Real(1) / sqrt(Real(1) + u0 * u0 + u1 * u1 + u2 * u2);
+    const Real igam = fast_rsqrt(Real(1) + u0 * u0 + u1 * u1 + u2 * u2);
     const Real vv[3] = {u0 * igam, u1 * igam, u2 * igam};
     int cn[3] = {0, 0, 0};
     Real fn[3] = {Real(0), Real(0), Real(0)}, dd[3] = {Real(0), Real(0), Real(0)};
@@ -399,37 +409,44 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     Acc* J1 = Jl + jcap;
     Acc* J2 = Jl + 2 * jcap;
     if (DIM == 2) {
+      // Slot L+1 of an axis (and the last prefix face along it) is nonzero
+      // only when the particle's stencil widened along that axis.
 #pragma unroll
       for (int v = 0; v < NU; ++v) {
-        const Real fy = S0u[1][v] + half * DSu[1][v];
+        if (v == L + 1 && !cross[1]) continue;
+        const Real fy = jx * (S0u[1][v] + half * DSu[1][v]);
         Acc* row = J0 + iu[0] + jwx * (iu[1] + v);
         Real acc = Real(0);
 #pragma unroll
-        for (int u = 0; u <= L; ++u) {
+        for (int u = 0; u < L; ++u) {
           acc += DSu[0][u] * fy;
-          // the prefix over all of S0's nodes is zero unless the stencil widened
-          if (u < L || cross[0]) lds_add<Acc>(row + u, Acc(jx * acc));
+          lds_add<Acc>(row + u, Acc(acc));
         }
+        if (cross[0]) lds_add<Acc>(row + L, Acc(acc + DSu[0][L] * fy));
       }
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
-        const Real fx = S0u[0][u] + half * DSu[0][u];
+        if (u == L + 1 && !cross[0]) continue;
+        const Real fx = jy * (S0u[0][u] + half * DSu[0][u]);
         Acc* col = J1 + iu[0] + u + jwx * iu[1];
         Real acc = Real(0);
 #pragma unroll
-        for (int v = 0; v <= L; ++v) {
+        for (int v = 0; v < L; ++v) {
           acc += DSu[1][v] * fx;
-          if (v < L || cross[1]) lds_add<Acc>(col + jwx * v, Acc(jy * acc));
+          lds_add<Acc>(col + jwx * v, Acc(acc));
         }
+        if (cross[1]) lds_add<Acc>(col + jwx * L, Acc(acc + DSu[1][L] * fx));
       }
       const Real vz = jz * vv[2];
 #pragma unroll
       for (int v = 0; v < NU; ++v) {
-        const Real Av = S0u[1][v] + half * DSu[1][v];
-        const Real Bv = half * S0u[1][v] + third * DSu[1][v];
+        if (v == L + 1 && !cross[1]) continue;
+        const Real Av = vz * (S0u[1][v] + half * DSu[1][v]);
+        const Real Bv = vz * (half * S0u[1][v] + third * DSu[1][v]);
         Acc* row = J2 + iu[0] + jwx * (iu[1] + v);
 #pragma unroll
-        for (int u = 0; u < NU; ++u) lds_add<Acc>(row + u, Acc(vz * (S0u[0][u] * Av + DSu[0][u] * Bv)));
+        for (int u = 0; u <= L; ++u) lds_add<Acc>(row + u, Acc(S0u[0][u] * Av + DSu[0][u] * Bv));
+        if (cross[0]) lds_add<Acc>(row + L + 1, Acc(S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv));
       }
     } else {
       // J1: prefix along x of DS_x * T_yz
@@ -437,6 +454,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int w = 0; w < NU; ++w) {
 #pragma unroll
         for (int v = 0; v < NU; ++v) {
+          if ((v == L + 1 && !cross[1]) || (w == L + 1 && !cross[2])) continue;
           const Real tr = S0u[1][v] * (S0u[2][w] + half * DSu[2][w]) +
                           DSu[1][v] * (half * S0u[2][w] + third * DSu[2][w]);
           Acc* row = J0 + iu[0] + jwx * (iu[1] + v + jwy * (iu[2] + w));
@@ -453,6 +471,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int w = 0; w < NU; ++w) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
+          if ((u == L + 1 && !cross[0]) || (w == L + 1 && !cross[2])) continue;
           const Real tr = S0u[0][u] * (S0u[2][w] + half * DSu[2][w]) +
                           DSu[0][u] * (half * S0u[2][w] + third * DSu[2][w]);
           Acc* col = J1 + iu[0] + u + jwx * (iu[1] + jwy * (iu[2] + w));
@@ -469,6 +488,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int v = 0; v < NU; ++v) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
+          if ((u == L + 1 && !cross[0]) || (v == L + 1 && !cross[1])) continue;
           const Real tr = S0u[0][u] * (S0u[1][v] + half * DSu[1][v]) +
                           DSu[0][u] * (half * S0u[1][v] + third * DSu[1][v]);
           Acc* col = J2 + iu[0] + u + jwx * (iu[1] + v + jwy * iu[2]);
@@ -581,29 +601,37 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   }
 }
 
+// Persistent workgroups: each takes tiles from a device queue until none are
+// left, so uneven tiles (edge tiles, runs of different size) balance.
 template <class P, int L, int DIM>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(gpd_block<DIM>())
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
                const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
   __shared__ int sred[8];
-  // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
-  // contiguous run of tiles so neighbouring windows share its L2.
-  const int b = blockIdx.x;
-  const int per = gridDim.x >> 3;
-  const int g = (b & 7) * per + (b >> 3);
-  if (g >= A.G) return;
-  const int kt = runs[tile_run[g]].KT;
-  if (kt == L + 1)
-    gpd_tile<P, L, DIM, L + 1>(A, runs, tile_run, g, lds_dyn, sred);
-  else
-    gpd_tile<P, L, DIM, L + 2>(A, runs, tile_run, g, lds_dyn, sred);
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(&A.st->tile_queue, 1);
+    __syncthreads();
+    const int g = next;
+    __syncthreads();
+    if (g >= A.G) return;
+    const int kt = runs[tile_run[g]].KT;
+    if (kt == L + 1)
+      gpd_tile<P, L, DIM, L + 1>(A, runs, tile_run, g, lds_dyn, sred);
+    else
+      gpd_tile<P, L, DIM, L + 2>(A, runs, tile_run, g, lds_dyn, sred);
+    __syncthreads();
+  }
 }
+
+__global__ void gpd_queue_reset(DevState* st) { st->tile_queue = 0; }
 
 template <class P, int L, int DIM>
 static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
-  const int grid = ((a.G + 7) / 8) * 8;
-  hipLaunchKernelGGL((gpd_kernel<P, L, DIM>), dim3(grid), dim3(256), lds, s, a, a.runs, a.tile_run);
+  const int grid = a.G < a.max_groups ? a.G : a.max_groups;
+  hipLaunchKernelGGL(gpd_queue_reset, dim3(1), dim3(1), 0, s, a.st);
+  hipLaunchKernelGGL((gpd_kernel<P, L, DIM>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs, a.tile_run);
   return hipGetLastError();
 }
 

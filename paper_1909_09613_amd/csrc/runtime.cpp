@@ -192,6 +192,7 @@ struct pic_ctx {
   int fw[3] = {1, 1, 1}, jw[3] = {1, 1, 1}, guard[3] = {0, 0, 0};
   size_t lds = 0;
   size_t lds_budget = 64 * 1024;
+  int max_groups = 2048;
   pic_buffers bufs{};
   Layout lay{};
   char* P = nullptr;
@@ -238,6 +239,14 @@ struct pic_ctx {
 };
 
 namespace {
+
+// Host <-> device transfer of pageable host memory: drain the context stream,
+// then a blocking copy that has completed when it returns.
+hipError_t host_copy(pic_ctx* c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && bytes > 0) e = hipMemcpy(dst, src, bytes, kind);
+  return e;
+}
 
 // Reach of a table's nodes relative to the particle's cell: base - cell is 0
 // or -1 (the latter only when sigma > 0).
@@ -370,10 +379,10 @@ pic_status apply_tiling(pic_ctx* c) {
   c->tile_run_host.assign(G, 0);
   for (int r = 0; r < c->nruns; ++r)
     for (int t = 0; t < c->runs[r].ntiles; ++t) c->tile_run_host[c->runs[r].tile0 + t] = r;
-  hipError_t e = hipMemcpyAsync(c->S + c->lay.s_runs, rd.data(), sizeof(RunDev<Real>) * rd.size(),
-                                hipMemcpyHostToDevice, c->stream);
+  hipError_t e = host_copy(c, c->S + c->lay.s_runs, rd.data(), sizeof(RunDev<Real>) * rd.size(),
+                                hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->S + c->lay.s_tile_run, c->tile_run_host.data(), 4 * G, hipMemcpyHostToDevice, c->stream);
+    e = host_copy(c, c->S + c->lay.s_tile_run, c->tile_run_host.data(), 4 * G, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return c->hip(e, "apply_tiling");
 }
@@ -387,11 +396,11 @@ pic_status upload_static(pic_ctx* c) {
       c->blk_run_host.push_back(r);
       c->blk_first_host.push_back((int)f);
     }
-  hipError_t e = hipMemcpyAsync(c->S + c->lay.s_blk_run, c->blk_run_host.data(), 4 * c->blk_run_host.size(),
-                                hipMemcpyHostToDevice, c->stream);
+  hipError_t e = host_copy(c, c->S + c->lay.s_blk_run, c->blk_run_host.data(), 4 * c->blk_run_host.size(),
+                                hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->S + c->lay.s_blk_first, c->blk_first_host.data(), 4 * c->blk_first_host.size(),
-                       hipMemcpyHostToDevice, c->stream);
+    e = host_copy(c, c->S + c->lay.s_blk_first, c->blk_first_host.data(), 4 * c->blk_first_host.size(),
+                       hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemsetAsync(c->F, 0, c->lay.bytes[1], c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->J, 0, c->lay.bytes[2], c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->P, 0, c->lay.bytes[0], c->stream);
@@ -414,6 +423,7 @@ GpdArgs<Real> gpd_args(pic_ctx* c) {
   a.J = c->J;
   a.ncell_total = c->ncell_total;
   a.G = c->G;
+  a.max_groups = c->max_groups;
   for (int k = 0; k < 3; ++k) {
     a.tile[k] = c->tile[k];
     a.fw[k] = c->fw[k];
@@ -512,7 +522,7 @@ pic_status do_fields(pic_ctx* c) { return c->f64() ? enqueue_fields<double>(c) :
 
 int read_parity(pic_ctx* c, pic_status* st) {
   DevState ds{};
-  hipError_t e = hipMemcpyAsync(&ds, c->state(), sizeof ds, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = host_copy(c, &ds, c->state(), sizeof ds, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   *st = c->hip(e, "read state");
   return ds.parity;
@@ -580,16 +590,16 @@ pic_status set_particles_t(pic_ctx* c, int run, int species, const double* x, co
   }
   const size_t rs = sizeof(Real);
   hipError_t e = hipSuccess;
-  if (!c->f64()) e = hipMemcpyAsync(c->P + c->lay.p_cell[par] + 4 * base, cell.data(), 4 * n, hipMemcpyHostToDevice, c->stream);
+  if (!c->f64()) e = host_copy(c, c->P + c->lay.p_cell[par] + 4 * base, cell.data(), 4 * n, hipMemcpyHostToDevice);
   for (int k = 0; k < c->ndim && e == hipSuccess; ++k)
-    e = hipMemcpyAsync(c->P + c->lay.p_pos[par][k] + rs * base, pos[k].data(), rs * n, hipMemcpyHostToDevice, c->stream);
+    e = host_copy(c, c->P + c->lay.p_pos[par][k] + rs * base, pos[k].data(), rs * n, hipMemcpyHostToDevice);
   for (int k = 0; k < 3 && e == hipSuccess; ++k)
-    e = hipMemcpyAsync(c->P + c->lay.p_u[par][k] + rs * base, uu[k].data(), rs * n, hipMemcpyHostToDevice, c->stream);
+    e = host_copy(c, c->P + c->lay.p_u[par][k] + rs * base, uu[k].data(), rs * n, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->P + c->lay.p_tag[par] + 4 * base, tag.data(), 4 * n, hipMemcpyHostToDevice, c->stream);
+    e = host_copy(c, c->P + c->lay.p_tag[par] + 4 * base, tag.data(), 4 * n, hipMemcpyHostToDevice);
   const int one = 1;
   if (e == hipSuccess)
-    e = hipMemcpyAsync(&c->state()->sort_request, &one, sizeof one, hipMemcpyHostToDevice, c->stream);
+    e = host_copy(c, &c->state()->sort_request, &one, sizeof one, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip(e, "set_particles");
   H.set[species] = true;
@@ -609,19 +619,18 @@ pic_status get_particles_t(pic_ctx* c, int run, int species, double* x, double* 
   std::vector<int> cell(c->f64() ? 0 : cnt), tag(cnt);
   std::vector<Real> pos[3], uu[3];
   hipError_t e = hipSuccess;
-  if (!c->f64()) e = hipMemcpyAsync(cell.data(), c->P + c->lay.p_cell[par] + 4 * base, 4 * cnt, hipMemcpyDeviceToHost, c->stream);
+  if (!c->f64()) e = host_copy(c, cell.data(), c->P + c->lay.p_cell[par] + 4 * base, 4 * cnt, hipMemcpyDeviceToHost);
   for (int k = 0; k < 3; ++k) {
     uu[k].resize(cnt);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(uu[k].data(), c->P + c->lay.p_u[par][k] + rs * base, rs * cnt, hipMemcpyDeviceToHost, c->stream);
+      e = host_copy(c, uu[k].data(), c->P + c->lay.p_u[par][k] + rs * base, rs * cnt, hipMemcpyDeviceToHost);
     if (k < c->ndim) {
       pos[k].resize(cnt);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(pos[k].data(), c->P + c->lay.p_pos[par][k] + rs * base, rs * cnt, hipMemcpyDeviceToHost,
-                           c->stream);
+        e = host_copy(c, pos[k].data(), c->P + c->lay.p_pos[par][k] + rs * base, rs * cnt, hipMemcpyDeviceToHost);
     }
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(tag.data(), c->P + c->lay.p_tag[par] + 4 * base, 4 * cnt, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = host_copy(c, tag.data(), c->P + c->lay.p_tag[par] + 4 * base, 4 * cnt, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip(e, "get_particles");
   long long found = 0;
@@ -664,17 +673,17 @@ pic_status fields_io(pic_ctx* c, int run, const double* Ein, const double* Bin, 
     Real* dev = F + comp * NT + H.cell0;
     if (src) {
       for (long long i = 0; i < nc; ++i) tmp[i] = Real(src[k * nc + i]);
-      e = hipMemcpyAsync(dev, tmp.data(), sizeof(Real) * nc, hipMemcpyHostToDevice, c->stream);
+      e = host_copy(c, dev, tmp.data(), sizeof(Real) * nc, hipMemcpyHostToDevice);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
     if (dst && e == hipSuccess) {
-      e = hipMemcpyAsync(tmp.data(), dev, sizeof(Real) * nc, hipMemcpyDeviceToHost, c->stream);
+      e = host_copy(c, tmp.data(), dev, sizeof(Real) * nc, hipMemcpyDeviceToHost);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       for (long long i = 0; i < nc; ++i) dst[k * nc + i] = (double)tmp[i];
     }
   }
   for (int k = 0; k < 3 && Jout && e == hipSuccess; ++k)
-    e = hipMemcpyAsync(Jout + k * nc, c->J + k * NT + H.cell0, 8 * nc, hipMemcpyDeviceToHost, c->stream);
+    e = host_copy(c, Jout + k * nc, c->J + k * NT + H.cell0, 8 * nc, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return c->hip(e, "field transfer");
 }
@@ -698,8 +707,8 @@ pic_status diag_t(pic_ctx* c, int run, pic_diag* out) {
   if (e == hipSuccess) e = launch_diag<P>(a, c->ndim, c->order, H.ncell, H.p0, 2 * H.nps, c->stream);
   double acc[16];
   DevState ds{};
-  if (e == hipSuccess) e = hipMemcpyAsync(acc, a.acc, sizeof acc, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&ds, c->state(), sizeof ds, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = host_copy(c, acc, a.acc, sizeof acc, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = host_copy(c, &ds, c->state(), sizeof ds, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip(e, "diagnostics");
   double Vc = 1.0;
@@ -802,20 +811,23 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
   // re-sorts are checked every 2 steps with a 3-cell margin; 3D windows are
   // costlier, so 3D checks every step with a 2-cell margin.
   {
-    int dev = 0, lim = 0;
+    int dev = 0, lim = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 0)
       c->lds_budget = std::min<size_t>((size_t)lim, (size_t)kMaxLds);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      c->max_groups = 8 * cus;  // more than fit at once; the extra ones find the queue empty
   }
-  static const int cand2[][3] = {{32, 16, 1}, {32, 8, 1}, {16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}};
+  // 16 x 16 measured fastest in 2D at both precisions (a wider tile stages
+  // more fields per particle than it saves in window overlap)
+  static const int cand2[][3] = {{16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}};
   static const int cand3[][3] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}};
-  const int ncand = (c->ndim == 2) ? 7 : 6;
+  const int ncand = (c->ndim == 2) ? 5 : 6;
   c->margin = (c->ndim == 2) ? 3 : 2;
   c->sort_every = (c->ndim == 2) ? 2 : 1;
   st = PIC_ERR_ARG;
   for (int i = 0; i < ncand && st != PIC_OK; ++i) {
     const int* t = (c->ndim == 2) ? cand2[i] : cand3[i];
-    if (c->ndim == 2 && c->f64() && t[0] > 16) continue;
     for (int k = 0; k < 3; ++k) c->tile[k] = t[k];
     st = c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c);
   }

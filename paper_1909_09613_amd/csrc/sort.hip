@@ -6,9 +6,12 @@
 // count   key = 2 * tile + species per particle; wave-aggregated counts
 // scan    one block: exclusive scan of the counts into segment offsets;
 //         reset every tile's box to its rectangle
-// scatter slot = segment start + (rank * prime mod segment size): particles
-//         of one cell land spread over the segment, so the lanes of a wave
-//         deposit into different LDS nodes
+// scatter ranks within a segment are read as a 16-row matrix and stored
+//         transposed (rank r -> row r mod 16, column r div 16): ranks arrive in
+//         the source order, where a cell's particles are consecutive, so
+//         consecutive slots -- the lanes of a wave -- take particles from
+//         different, neighbouring cells and their LDS accesses spread over
+//         the banks instead of piling onto one stencil
 // flip    swap the particle stores, clear the request
 #include "common.hpp"
 #include "launch.hpp"
@@ -17,7 +20,7 @@ namespace wtpic {
 
 namespace {
 
-constexpr unsigned long long kSpread = 1000003ull;  // prime above any segment size
+constexpr int kInterleave = 16;  // rows of the rank transposition
 
 template <class Real>
 __device__ int find_run(const RunDev<Real>* runs, int nruns, long long p) {
@@ -165,10 +168,11 @@ __global__ void sort_scatter(SortArgs<typename P::Real> A) {
     if (!valid) continue;
     const int s0 = A.seg[key];
     const int n = A.seg[key + 1] - s0;
-    const unsigned long long slot =
-        (n > 0 && (unsigned long long)n < kSpread) ? ((unsigned long long)rank * kSpread) % (unsigned long long)n
-                                                   : (unsigned long long)rank;
-    const long long q = s0 + (long long)slot;
+    // transposed position: row ii holds ranks ii, ii + 16, ...; the first
+    // n mod 16 rows have one entry more than the others
+    const int nq = n / kInterleave, rem = n % kInterleave;
+    const int ii = rank % kInterleave, mm = rank / kInterleave;
+    const long long q = s0 + (long long)(ii * nq + min(ii, rem) + mm);
     if (!P::kAbs) D.cell[q] = S.cell[p];
     for (int d = 0; d < DIM; ++d) D.pos[d][q] = S.pos[d][p];
     D.u[0][q] = S.u[0][p];
