@@ -965,10 +965,8 @@ pic_status pic_diagnostics(pic_ctx* c, int32_t run, pic_diag* out) {
   if (run < 0 || run >= c->nruns || !out) return c->fail(PIC_ERR_ARG, "bad run or NULL out");
   pic_status st = check_ready(c);
   if (st != PIC_OK) return st;
-  if (c->force_sort) {
-    // particles were just set: order them so the box/segment state is valid
-    return c->fail(PIC_ERR_STATE, "take a step before diagnostics after setting particles");
-  }
+  // the diagnostic kernels take a particle's species from its tag, so they
+  // read the stores in any order (also right after pic_set_particles)
   return c->f64() ? diag_t<F64>(c, run, out) : diag_t<F32>(c, run, out);
 }
 

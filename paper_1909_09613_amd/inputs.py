@@ -90,16 +90,18 @@ def drifting_momenta(rng, n, gamma0, u_th):
     return u
 
 
-def stratified_positions(rng, spec):
-    """(ncell*ppc_s, 3) positions in cell units, ppc_s per cell, cell-major."""
+def stratified_positions(rng, spec, p0, p1):
+    """(p1 - p0, 3) positions in cell units of particles p0..p1-1, where
+    particle p sits in cell p // ppc_s (cell-major, x fastest)."""
     n3 = spec.n3
-    ii, jj, kk = np.meshgrid(np.arange(n3[0]), np.arange(n3[1]), np.arange(n3[2]), indexing="ij")
-    base = np.stack([ii.ravel(order="F"), jj.ravel(order="F"), kk.ravel(order="F")], axis=1)
-    base = np.repeat(base.astype(np.float64), spec.ppc_s, axis=0)
-    off = rng.random(base.shape)
+    cell = np.arange(p0, p1, dtype=np.int64) // spec.ppc_s
+    base = np.empty((p1 - p0, 3), dtype=np.float64)
+    base[:, 0] = cell % n3[0]
+    base[:, 1] = (cell // n3[0]) % n3[1]
+    base[:, 2] = cell // (n3[0] * n3[1])
+    off = rng.random((p1 - p0, 3))
     if spec.ndim == 2:
         off[:, 2] = 0.0
-        base[:, 2] = 0.0
     x = base + off
     # an offset that rounds the position onto the upper cell face stays in range
     for d in range(spec.ndim):
@@ -107,16 +109,49 @@ def stratified_positions(rng, spec):
     return x
 
 
-def make_species(spec):
+CHUNK = 1 << 20   # particles per independent random stream
+
+
+def make_species(spec, workers=None):
     """Electron and positron arrays for one run.
 
-    Returns a list of dicts {x, u, qm, Q, M} with x, u of shape (np, 3).
+    Particles are drawn in chunks of about CHUNK particles (whole cells), each
+    from its own PCG64 stream spawned from ``spec.seed``, so that large
+    workloads are generated in parallel and the result does not depend on
+    the number of workers.  Returns a list of dicts {x, u, qm, Q, M} with x, u
+    of shape (np, 3).
     """
-    rng = np.random.Generator(np.random.PCG64(spec.seed))
-    xe = stratified_positions(rng, spec)
-    xp = xe.copy() if spec.colocated else stratified_positions(rng, spec)
-    ue = drifting_momenta(rng, len(xe), spec.gamma0, spec.u_th)
-    up = drifting_momenta(rng, len(xp), spec.gamma0, spec.u_th)
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+
+    n = spec.ncell * spec.ppc_s
+    per = max(1, CHUNK // spec.ppc_s) * spec.ppc_s
+    bounds = [(p, min(p + per, n)) for p in range(0, n, per)]
+    seeds = np.random.SeedSequence(spec.seed).spawn(len(bounds))
+    xe = np.empty((n, 3))
+    xp = xe if spec.colocated else np.empty((n, 3))
+    ue = np.empty((n, 3))
+    up = np.empty((n, 3))
+
+    def fill(k):
+        p0, p1 = bounds[k]
+        rng = np.random.Generator(np.random.PCG64(seeds[k]))
+        xe[p0:p1] = stratified_positions(rng, spec, p0, p1)
+        if not spec.colocated:
+            xp[p0:p1] = stratified_positions(rng, spec, p0, p1)
+        ue[p0:p1] = drifting_momenta(rng, p1 - p0, spec.gamma0, spec.u_th)
+        up[p0:p1] = drifting_momenta(rng, p1 - p0, spec.gamma0, spec.u_th)
+
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if len(bounds) == 1 or workers <= 1:
+        for k in range(len(bounds)):
+            fill(k)
+    else:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(fill, range(len(bounds))))
+    if spec.colocated:
+        xp = xe.copy()
     out = []
     for (qm, Q, M), x, u in zip(spec.species_constants(), (xe, xp), (ue, up)):
         out.append({"x": x, "u": u, "qm": qm, "Q": Q, "M": M})

@@ -88,11 +88,6 @@ CASES_3D = [
 ]
 
 
-def _transverse(spec, k):
-    """Current components driven by the thermal (transverse) motion only."""
-    return k == 1 or (spec.ndim == 3 and k == 2)
-
-
 def _ids(cases):
     return ["%dd-l%d-a%.2f-%s" % (c.ndim, c.order, c.courant, "x".join(map(str, c.n))) for c in cases]
 
@@ -103,7 +98,7 @@ def test_one_step_fp64(orc, spec):
     assert ex <= 1e-12
     assert eu <= 1e-12
     for k in range(3):
-        assert ej[k] <= (1e-11 if _transverse(spec, k) else 1e-12)
+        assert ej[k] <= H.current_tol(spec, k, False)
 
 
 @pytest.mark.parametrize("spec", CASES_2D + CASES_3D, ids=_ids(CASES_2D + CASES_3D))
@@ -112,7 +107,7 @@ def test_one_step_fp32(orc, spec):
     assert ex <= 2e-6
     assert eu <= 2e-6
     for k in range(3):
-        assert ej[k] <= (2e-4 if _transverse(spec, k) else 1e-5)
+        assert ej[k] <= H.current_tol(spec, k, True)
 
 
 @pytest.mark.parametrize("ndim,solver", [(2, 0), (2, 1), (3, 0), (3, 1)])

@@ -1,0 +1,170 @@
+"""Multi-step physics of the GPU path: the numerical Cherenkov instability
+(NCI) of a drifting pair plasma, the quantity the WT scheme exists to
+suppress (Sec. 3, Fig. 1).  The paper prints no growth-rate table, so the
+absolute rates are parity unpinned; what is tested is what the paper states
+qualitatively, plus the FP32 path against the FP64 path:
+
+  * MC, Yee: c dt = dt_CFL / sqrt(2) (a = 1/2 in 2D) grows far slower than
+    the other time steps (the lowest-order growth rate vanishes there);
+  * WT grows far slower than MC at the same time step, and slower the
+    smaller the time step;
+  * WT at a = 1/2 is the MC scheme;
+  * FP32 mixed vs FP64: fitted growth rate within 5 %, peak level within 20 %.
+
+Workloads: 2D 256 x 128, l = 3, gamma0 = 50, u_th = 0.01, 8 particles per cell
+per species, run to t = 1500 dx/c (about 94 / omega_pe); and the paper's
+Table 1 problem (l = 4, 256 x 128, 32 per cell per species, gamma0 = 1000,
+k_B T = 0.01 m c^2) for the MC-limit statement.
+"""
+import numpy as np
+import pytest
+
+import paper_1909_09613_amd as wt
+from paper_1909_09613_amd import inputs
+from paper_1909_09613_amd.inputs import RunSpec
+
+pytestmark = pytest.mark.gpu
+
+T_END = 1500.0
+T_SAMPLE = 4.0
+
+
+def _history(spec, precision, t_end=T_END):
+    """Field energy U_E + U_B sampled every ~T_SAMPLE time units, and the
+    initial kinetic energy."""
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, inputs.make_species(spec))
+        E0 = sum(sim.diagnostics(0).Ekin)
+        a = spec.courant
+        steps = int(round(t_end / a))
+        every = max(1, int(round(T_SAMPLE / a)))
+        t, U, done = [], [], 0
+        while done < steps:
+            k = min(every, steps - done)
+            sim.step(k)
+            done += k
+            d = sim.diagnostics(0)
+            t.append(done * a)
+            U.append(sum(d.UE) + sum(d.UB))
+    finally:
+        sim.close()
+    return np.array(t), np.array(U), E0
+
+
+def _at(t, U, when):
+    return U[int(np.argmin(np.abs(t - when)))]
+
+
+def growth_rate(t, U, t_skip=150.0, win=20):
+    """Least-squares slope of ln U over the window around the steepest
+    stretch where the win-sample local slope stays >= 80 % of its maximum;
+    samples before t_skip (the thermal-noise transient) are left out."""
+    keep = t >= t_skip
+    t, y = t[keep], np.log(U[keep])
+    sl = (y[win:] - y[:-win]) / (t[win:] - t[:-win])
+    k = int(np.argmax(sl))
+    lo = hi = k
+    while lo > 0 and sl[lo - 1] >= 0.8 * sl[k]:
+        lo -= 1
+    while hi + 1 < len(sl) and sl[hi + 1] >= 0.8 * sl[k]:
+        hi += 1
+    return float(np.polyfit(t[lo:hi + win + 1], y[lo:hi + win + 1], 1)[0])
+
+
+def _spec(scheme, a, **kw):
+    return RunSpec(2, (256, 128), 3, a, 50.0, 0.01, 8, 77, scheme=scheme, **kw)
+
+
+@pytest.fixture(scope="module")
+def runs():
+    out = {}
+    for scheme in (wt.PIC_WT, wt.PIC_MC):
+        for a in (0.25, 0.45, 0.5, 0.6, 0.7):
+            out[(scheme, a, wt.PIC_MIXED32)] = _history(_spec(scheme, a), wt.PIC_MIXED32)
+        out[(scheme, 0.45, wt.PIC_FP64)] = _history(_spec(scheme, 0.45), wt.PIC_FP64)
+    for k, (t, U, E0) in sorted(out.items()):
+        print("nci %s a=%.2f %s: log10 U/E0 at t=300,600,1500: %.2f %.2f %.2f" % (
+            "WT" if k[0] == wt.PIC_WT else "MC", k[1], "fp32" if k[2] == wt.PIC_MIXED32 else "fp64",
+            np.log10(_at(t, U, 300) / E0), np.log10(_at(t, U, 600) / E0), np.log10(U[-1] / E0)), flush=True)
+    return out
+
+
+def test_mc_nci_slowest_at_mc_limit(runs):
+    t, U, _ = runs[(wt.PIC_MC, 0.5, wt.PIC_MIXED32)]
+    u_half = _at(t, U, 600)
+    for a in (0.25, 0.45, 0.6, 0.7):
+        t2, U2, _ = runs[(wt.PIC_MC, a, wt.PIC_MIXED32)]
+        assert np.log10(_at(t2, U2, 600) / u_half) >= 3.0, a
+
+
+def test_wt_suppresses_nci_relative_to_mc(runs):
+    for a in (0.25, 0.45):
+        _, Uw, _ = runs[(wt.PIC_WT, a, wt.PIC_MIXED32)]
+        _, Um, _ = runs[(wt.PIC_MC, a, wt.PIC_MIXED32)]
+        assert Uw.max() <= 1e-2 * Um.max(), a
+
+
+def test_wt_nci_grows_slower_with_smaller_dt(runs):
+    ends = [runs[(wt.PIC_WT, a, wt.PIC_MIXED32)][1][-1] for a in (0.25, 0.45, 0.6, 0.7)]
+    assert all(x < y for x, y in zip(ends, ends[1:])), ends
+    # at the smallest step the field stays near the thermal level
+    _, U, E0 = runs[(wt.PIC_WT, 0.25, wt.PIC_MIXED32)]
+    assert U[-1] / E0 <= 1e-4
+
+
+def test_wt_is_mc_at_half(runs):
+    """The FP32 histories agree to the level at which the (unordered) atomic
+    current sums perturb an FP32 state; one FP64 step agrees to round-off."""
+    t, Uw, _ = runs[(wt.PIC_WT, 0.5, wt.PIC_MIXED32)]
+    _, Um, _ = runs[(wt.PIC_MC, 0.5, wt.PIC_MIXED32)]
+    rel = np.abs(Uw - Um) / Um
+    print("WT vs MC at a=1/2: max rel diff t<=300 %.2e, whole run %.2e" % (rel[t <= 300].max(), rel.max()), flush=True)
+    assert rel[t <= 300].max() <= 1e-5
+    assert rel.max() <= 1e-3
+    spec_w = RunSpec(2, (64, 48), 3, 0.5, 50.0, 0.01, 4, 78, scheme=wt.PIC_WT)
+    spec_m = RunSpec(2, (64, 48), 3, 0.5, 50.0, 0.01, 4, 78, scheme=wt.PIC_MC)
+    rng = np.random.default_rng(3)
+    E = inputs.random_fields(rng, spec_w.ncell, 0.05)
+    B = inputs.random_fields(rng, spec_w.ncell, 0.05)
+    got = []
+    for spec in (spec_w, spec_m):
+        sim = wt.Sim([spec], wt.PIC_FP64)
+        try:
+            sim.set_species(0, inputs.make_species(spec))
+            sim.set_fields(0, E, B)
+            sim.gpd()
+            got.append(([sim.particles(0, k) for k in range(2)], sim.fields(0)[2]))
+        finally:
+            sim.close()
+    (pw, Jw), (pm, Jm) = got
+    for k in range(2):
+        assert np.max(np.abs(pw[k][0] - pm[k][0])) <= 1e-13
+        assert np.max(np.abs(pw[k][1] - pm[k][1])) <= 1e-13 * np.max(np.abs(pm[k][1]))
+    # scale of what was summed: both species' charge density moving at c
+    q = abs(spec_w.species_constants()[0][1])
+    assert np.max(np.abs(Jw - Jm)) <= 1e-13 * 2 * spec_w.ppc_s * q * spec_w.c / spec_w.Vc
+
+
+@pytest.mark.parametrize("scheme", [wt.PIC_MC, wt.PIC_WT], ids=["MC", "WT"])
+def test_fp32_matches_fp64_nci(runs, scheme):
+    t32, U32, _ = runs[(scheme, 0.45, wt.PIC_MIXED32)]
+    t64, U64, _ = runs[(scheme, 0.45, wt.PIC_FP64)]
+    g32, g64 = growth_rate(t32, U32), growth_rate(t64, U64)
+    print("growth rate a=0.45 %s: fp32 %.5f fp64 %.5f; peak %.4e %.4e" % (
+        "MC" if scheme == wt.PIC_MC else "WT", g32, g64, U32.max(), U64.max()), flush=True)
+    assert g64 > 0
+    assert abs(g32 - g64) <= 0.05 * g64
+    assert abs(U32.max() - U64.max()) <= 0.2 * U64.max()
+
+
+def test_table1_mc4_slowest_at_mc_limit():
+    """Table 1 problem with MC4 + Yee: dt = dt_CFL/sqrt(2) against 0.5 dt_CFL."""
+    out = {}
+    for r in (0.5, 2 ** -0.5):
+        spec = RunSpec(2, (256, 128), 4, r / np.sqrt(2.0), 1000.0, 0.1, 32, 91, scheme=wt.PIC_MC)
+        out[r] = _history(spec, wt.PIC_MIXED32, t_end=600.0)
+    (t1, U1, E0), (t2, U2, _) = out[0.5], out[2 ** -0.5]
+    print("table1 MC4: log10 E/E0 at t=600: dt=0.5 dt_CFL %.2f, dt_CFL/sqrt2 %.2f" % (
+        np.log10(U1[-1] / E0), np.log10(U2[-1] / E0)), flush=True)
+    assert np.log10(U1[-1] / U2[-1]) >= 3.0
