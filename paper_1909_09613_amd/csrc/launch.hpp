@@ -17,6 +17,8 @@ struct SortArgs {
   int G;
   int nkeys;          // 2 G
   int tile[3];
+  int tc;             // cells of a full tile
+  int kcap;           // ranks within a cell ordered level by level (arrange pass)
   int* counts;        // nkeys
   int* cursor;        // nkeys
   int* seg;           // nkeys + 1
@@ -24,6 +26,17 @@ struct SortArgs {
   int* bbox;          // 6 G
   const int* tile_run;
 };
+
+// Block size and LDS bytes of the per-segment arrange pass of the sort.
+constexpr int kArrangeBlock = 512;
+inline size_t arrange_lds(int tc, int kcap) {
+  return (size_t)4 * (2 * tc + kcap + 2) + (size_t)2 * kcap * tc + 16;
+}
+// Levels the arrange pass orders one by one for a tile of tc cells.
+inline int arrange_kcap(int tc) {
+  const int k = 8192 / (tc > 0 ? tc : 1);
+  return k < 1 ? 1 : (k > 64 ? 64 : k);
+}
 
 template <class Real>
 struct FieldArgs {

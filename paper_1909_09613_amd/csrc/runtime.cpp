@@ -21,6 +21,7 @@ thread_local std::string g_err = "no error";
 // smallest tile edge; bounds the scratch layout
 int min_tile(int ndim) { return ndim == 2 ? 4 : 2; }
 constexpr int kMaxLds = 64 * 1024; // per-workgroup LDS budget of the particle kernel
+constexpr int kMaxTileCells = 4096; // the sort orders a tile's cells in LDS
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -344,6 +345,8 @@ pic_status apply_tiling(pic_ctx* c) {
     G += H.ntiles;
   }
   if (G > c->lay.gmax) return c->fail(PIC_ERR_ARG, "tile too small for the scratch layout");
+  if ((long long)c->tile[0] * c->tile[1] * c->tile[2] > kMaxTileCells)
+    return c->fail(PIC_ERR_ARG, "tile has more cells than the sort's arrange pass supports");
   c->G = (int)G;
   std::vector<RunDev<Real>> rd;
   pic_status st = build_runs<Real>(c, rd);
@@ -445,6 +448,8 @@ SortArgs<Real> sort_args(pic_ctx* c) {
   a.G = c->G;
   a.nkeys = 2 * c->G;
   for (int k = 0; k < 3; ++k) a.tile[k] = c->tile[k];
+  a.tc = c->tile[0] * c->tile[1] * c->tile[2];
+  a.kcap = arrange_kcap(a.tc);
   a.counts = reinterpret_cast<int*>(c->S + c->lay.s_counts);
   a.cursor = reinterpret_cast<int*>(c->S + c->lay.s_cursor);
   a.seg = reinterpret_cast<int*>(c->S + c->lay.s_seg);

@@ -2,25 +2,25 @@
 // particles have outgrown the staging margin of the gather-push-deposit
 // kernel (a device-side request flag; all kernels exit at once otherwise).
 //
-// prep    one block: latch the request, clear counters
-// count   key = 2 * tile + species per particle; wave-aggregated counts
-// scan    one block: exclusive scan of the counts into segment offsets;
-//         reset every tile's box to its rectangle
-// scatter ranks within a segment are read as a 16-row matrix and stored
-//         transposed (rank r -> row r mod 16, column r div 16): ranks arrive in
-//         the source order, where a cell's particles are consecutive, so
-//         consecutive slots -- the lanes of a wave -- take particles from
-//         different, neighbouring cells and their LDS accesses spread over
-//         the banks instead of piling onto one stencil
-// flip    swap the particle stores, clear the request
+// prep     one block: latch the request, clear counters
+// count    key = 2 * tile + species per particle; wave-aggregated counts
+// scan     one block: exclusive scan of the counts into segment offsets;
+//          reset every tile's box to its rectangle
+// scatter  each particle to its segment of the other store
+// arrange  one block per segment: order the segment back into the current
+//          store by (rank within its cell, cell): first every cell's first
+//          particle, cells in tile order, then every cell's second particle,
+//          and so on.  The lanes of a wave then hold particles of 64
+//          neighbouring cells, one each, so that the gather reads and the
+//          current atomics of a wave touch consecutive LDS addresses.  Ranks
+//          beyond `kcap` (dense cells) follow in cell order.
+// flip     clear the request, count the sort
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace wtpic {
 
 namespace {
-
-constexpr int kInterleave = 16;  // rows of the rank transposition
 
 template <class Real>
 __device__ int find_run(const RunDev<Real>* runs, int nruns, long long p) {
@@ -166,13 +166,7 @@ __global__ void sort_scatter(SortArgs<typename P::Real> A) {
     const int key = valid ? A.keys[p] : 0;
     const int rank = wave_add(A.cursor, key, valid);
     if (!valid) continue;
-    const int s0 = A.seg[key];
-    const int n = A.seg[key + 1] - s0;
-    // transposed position: row ii holds ranks ii, ii + 16, ...; the first
-    // n mod 16 rows have one entry more than the others
-    const int nq = n / kInterleave, rem = n % kInterleave;
-    const int ii = rank % kInterleave, mm = rank / kInterleave;
-    const long long q = s0 + (long long)(ii * nq + min(ii, rem) + mm);
+    const long long q = A.seg[key] + (long long)rank;
     if (!P::kAbs) D.cell[q] = S.cell[p];
     for (int d = 0; d < DIM; ++d) D.pos[d][q] = S.pos[d][p];
     D.u[0][q] = S.u[0][p];
@@ -182,10 +176,116 @@ __global__ void sort_scatter(SortArgs<typename P::Real> A) {
   }
 }
 
+// Tile-relative linear index of a particle's cell (tile order: x fastest).
+template <class P, int DIM>
+__device__ __forceinline__ int cell_in_tile(const PBuf<typename P::Real>& S, long long q, const int org[3],
+                                            const int tile[3]) {
+  int c[3] = {0, 0, 0};
+  if (P::kAbs) {
+    for (int d = 0; d < DIM; ++d) c[d] = (int)floor(S.pos[d][q]);
+  } else {
+    unpack_cell<DIM>(S.cell[q], c[0], c[1], c[2]);
+  }
+  int cl = 0, stride = 1;
+  for (int d = 0; d < DIM; ++d) {
+    // a particle lies in its tile's rectangle; clamp anyway so that any
+    // value gives a valid (if unordered) placement
+    const int m = min(max(c[d] - org[d], 0), tile[d] - 1);
+    cl += m * stride;
+    stride *= tile[d];
+  }
+  return cl;
+}
+
+template <class P, int DIM>
+__global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename P::Real> A) {
+  using Real = typename P::Real;
+  if (!A.st->sort_active) return;
+  extern __shared__ __align__(16) int sm[];
+  const int TC = A.tc, KC = A.kcap;
+  int* cnt = sm;                                                // TC: particles per cell
+  int* xpre = cnt + TC;                                         // TC + 1: prefix of ranks >= KC
+  int* base = xpre + TC + 1;                                    // KC + 1: slots below level k
+  unsigned short* pre = reinterpret_cast<unsigned short*>(base + KC + 1);  // KC x TC
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int nwave = kArrangeBlock / 64;
+  const int par = A.st->parity;
+  const PBuf<Real> S = A.buf[par ^ 1];
+  const PBuf<Real> D = A.buf[par];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int key = blockIdx.x; key < A.nkeys; key += gridDim.x) {
+    const int s0 = A.seg[key];
+    const int n = A.seg[key + 1] - s0;
+    if (n == 0) continue;
+    const int g = key >> 1;
+    const RunDev<Real>& R = A.runs[A.tile_run[g]];
+    const int lt = g - R.tile0;
+    int org[3];
+    org[0] = (lt % R.ntile[0]) * A.tile[0];
+    org[1] = ((lt / R.ntile[0]) % R.ntile[1]) * A.tile[1];
+    org[2] = (DIM == 3) ? (lt / (R.ntile[0] * R.ntile[1])) * A.tile[2] : 0;
+    for (int i = tid; i < TC; i += kArrangeBlock) cnt[i] = 0;
+    __syncthreads();
+    // rank of each particle within its cell
+    for (int i = tid; i < n; i += kArrangeBlock) {
+      const long long q = s0 + (long long)i;
+      A.keys[q] = atomicAdd(&cnt[cell_in_tile<P, DIM>(S, q, org, A.tile)], 1);
+    }
+    __syncthreads();
+    // level k < KC: cells holding more than k particles, numbered in cell order
+    for (int k = wave; k < KC; k += nwave) {
+      int run = 0;
+      for (int c0 = 0; c0 < TC; c0 += 64) {
+        const int c = c0 + lane;
+        const bool f = c < TC && cnt[c] > k;
+        const unsigned long long b = __ballot(f);
+        if (c < TC) pre[k * TC + c] = (unsigned short)(run + __popcll(b & below));
+        run += __popcll(b);
+      }
+      if (lane == 0) base[k + 1] = run;
+    }
+    // ranks >= KC: exclusive prefix over cells of max(0, count - KC)
+    if (wave == 0) {
+      int run = 0;
+      for (int c0 = 0; c0 < TC; c0 += 64) {
+        const int c = c0 + lane;
+        const int v = c < TC ? max(0, cnt[c] - KC) : 0;
+        int incl = v;
+        for (int off = 1; off < 64; off <<= 1) {
+          const int t = __shfl_up(incl, off);
+          if (lane >= off) incl += t;
+        }
+        if (c < TC) xpre[c] = run + incl - v;
+        run += __shfl(incl, 63);
+      }
+      if (lane == 0) xpre[TC] = run;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      base[0] = 0;
+      for (int k = 0; k < KC; ++k) base[k + 1] += base[k];
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += kArrangeBlock) {
+      const long long q = s0 + (long long)i;
+      const int cl = cell_in_tile<P, DIM>(S, q, org, A.tile);
+      const int k = A.keys[q];
+      const int slot = (k < KC) ? base[k] + (int)pre[k * TC + cl] : base[KC] + xpre[cl] + (k - KC);
+      const long long o = s0 + (long long)slot;
+      if (!P::kAbs) D.cell[o] = S.cell[q];
+      for (int d = 0; d < DIM; ++d) D.pos[d][o] = S.pos[d][q];
+      D.u[0][o] = S.u[0][q];
+      D.u[1][o] = S.u[1][q];
+      D.u[2][o] = S.u[2][q];
+      D.tag[o] = S.tag[q];
+    }
+    __syncthreads();
+  }
+}
+
 template <class Real>
 __global__ void sort_flip(SortArgs<Real> A) {
   if (!A.st->sort_active) return;
-  A.st->parity ^= 1;
   A.st->sort_request = 0;
   A.st->sort_active = 0;
   A.st->n_sorts += 1;
@@ -206,6 +306,11 @@ hipError_t launch_sort(const SortArgs<typename P::Real>& a, int ndim, hipStream_
     hipLaunchKernelGGL((sort_scatter<P, 2>), dim3(grid), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((sort_scatter<P, 3>), dim3(grid), dim3(256), 0, s, a);
+  const int agrid = a.nkeys < 2048 ? a.nkeys : 2048;
+  if (ndim == 2)
+    hipLaunchKernelGGL((sort_arrange<P, 2>), dim3(agrid), dim3(kArrangeBlock), arrange_lds(a.tc, a.kcap), s, a);
+  else
+    hipLaunchKernelGGL((sort_arrange<P, 3>), dim3(agrid), dim3(kArrangeBlock), arrange_lds(a.tc, a.kcap), s, a);
   hipLaunchKernelGGL(sort_flip<Real>, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }
