@@ -78,6 +78,16 @@ __device__ __forceinline__ void lds_add(Acc* p, Acc v) {
   atomicAdd(p, v);
 }
 
+// m mod n for -2n < m < 2n, without an integer division.  The box keeps
+// its centre in [0, n) and a cell index and a tile origin lie in [0, n), so
+// a particle's offset from the box's low end stays in that range.
+__device__ __forceinline__ int wrap_near(int m, int n) {
+  m += (m < 0) ? n : 0;
+  m += (m < 0) ? n : 0;
+  m -= (m >= n) ? n : 0;
+  return m;
+}
+
 // 1 / sqrt(x) and 1 / x: hardware approximations (1 ulp) for FP32, IEEE for FP64.
 __device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
@@ -228,7 +238,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       const int n = R.n[d];
       const int slack = max(0, n - 1 - (bb[2 * d + 1] - bb[2 * d]));
       const int lo = bb[2 * d] - (slack >> 1);
-      int rr = wrapi(c[d] - org[d] - lo, n) + lo;
+      int rr = wrap_near(c[d] - org[d] - lo, n) + lo;
       rel[d] = rr;
       inwin = inwin && (rr + R.glo[d] >= fo[d]) && (rr + R.ghi[d] < fo[d] + fs[d]) &&
               (rr + R.dlo[d] >= jo[d]) && (rr + R.dhi[d] < jo[d] + jsz[d]);

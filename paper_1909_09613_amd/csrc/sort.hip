@@ -11,9 +11,9 @@
 //          store by (rank within its cell, cell): first every cell's first
 //          particle, cells in tile order, then every cell's second particle,
 //          and so on.  The lanes of a wave then hold particles of 64
-//          neighbouring cells, one each, so that the gather reads and the
-//          current atomics of a wave touch consecutive LDS addresses.  Ranks
-//          beyond `kcap` (dense cells) follow in cell order.
+//          nearby cells, one each, so that the gather reads and the current
+//          atomics of a wave touch distinct, nearly consecutive LDS
+//          addresses.  Ranks beyond `kcap` (dense cells) follow in cell order.
 // flip     clear the request, count the sort
 #include "common.hpp"
 #include "launch.hpp"
@@ -176,7 +176,12 @@ __global__ void sort_scatter(SortArgs<typename P::Real> A) {
   }
 }
 
-// Tile-relative linear index of a particle's cell (tile order: x fastest).
+// Index of a particle's cell in the order the arrange pass lays cells out:
+// with an even tile width, first the cells of even x, then those of odd x
+// (each in x-then-y-then-z order), so that the lanes of a wave sit two cells
+// apart along x and particles that drift at slightly different times still
+// fall in different cells (same-address LDS atomics serialise); otherwise
+// plain x-fastest order.
 template <class P, int DIM>
 __device__ __forceinline__ int cell_in_tile(const PBuf<typename P::Real>& S, long long q, const int org[3],
                                             const int tile[3]) {
@@ -186,12 +191,17 @@ __device__ __forceinline__ int cell_in_tile(const PBuf<typename P::Real>& S, lon
   } else {
     unpack_cell<DIM>(S.cell[q], c[0], c[1], c[2]);
   }
+  int m[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) m[d] = min(max(c[d] - org[d], 0), tile[d] - 1);
+  if ((tile[0] & 1) == 0) {
+    const int h = tile[0] >> 1;
+    const int rest = m[1] + tile[1] * m[2];
+    const int nrest = tile[1] * (DIM == 3 ? tile[2] : 1);
+    return (m[0] & 1) * h * nrest + rest * h + (m[0] >> 1);
+  }
   int cl = 0, stride = 1;
   for (int d = 0; d < DIM; ++d) {
-    // a particle lies in its tile's rectangle; clamp anyway so that any
-    // value gives a valid (if unordered) placement
-    const int m = min(max(c[d] - org[d], 0), tile[d] - 1);
-    cl += m * stride;
+    cl += m[d] * stride;
     stride *= tile[d];
   }
   return cl;
