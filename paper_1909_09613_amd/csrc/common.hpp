@@ -100,6 +100,7 @@ struct GpdArgs {
   const int* tile_run;   // run of each global tile
   const int* seg;        // 2G+1 segment offsets: key 2g+s covers [seg[key], seg[key+1])
   int* bbox;             // per tile: lo0, hi0, lo1, hi1, lo2, hi2 (cells, tile-relative)
+  float* jb;             // per tile: bounds of the current contributions and cell counts (gpd.hip)
   DevState* st;
   PBuf<Real> buf[2];
   const Real* F;         // E1 E2 E3 B1 B2 B3, each ncell_total

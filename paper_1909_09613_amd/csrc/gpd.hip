@@ -78,6 +78,15 @@ __device__ __forceinline__ void lds_add(Acc* p, Acc v) {
   atomicAdd(p, v);
 }
 
+// Fixed-point LDS accumulation modulo 2^32; v is in units of the tile's
+// quantum and rounded to the nearest integer.
+__device__ __forceinline__ void lds_addq(int* p, float v) {
+  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)(int)rintf(v));
+}
+__device__ __forceinline__ void lds_addq(int* p, double v) {
+  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)(int)rint(v));
+}
+
 // m mod n for -2n < m < 2n, without an integer division.  The box keeps
 // its centre in [0, n) and a cell index and a tile origin lie in [0, n), so
 // a particle's offset from the box's low end stays in that range.
@@ -153,6 +162,40 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   const long long NT = A.ncell_total;
   const Real* Fg = A.F + R.cell0;
 
+  // Mixed precision accumulates the tile's current as 32-bit fixed point
+  // (FP64 LDS atomics cost about twice as much as integer ones, FP32 LDS
+  // atomics far more).  Every contribution of a particle to component c is
+  // bounded by |js_c| m_c, where m_c is the particle's step |d_c| along
+  // axis c (a prefix sum of S1 - S0 changes by at most the step, and the
+  // path-averaged transverse shapes lie in [0, 1]), or |v3| for the
+  // out-of-plane current in 2D.  A node receives contributions only from
+  // particles whose cell lies within l + 3 cells of it per axis, at most
+  // (l + 3)^d times the tile's largest count of particles in one cell.  The
+  // quantum is chosen so that this many particles with m_c <= thr_c
+  // (thr_c = 2 * the tile's largest m_c of the previous step, or of the
+  // stored velocities after a sort) give a node value below 2^31 quanta;
+  // the sums are taken modulo 2^32, so only the final value must fit.  A
+  // particle above a threshold deposits into FP64 LDS windows instead.
+  constexpr bool kFix = !P::kAbs;
+  Real qinv[3] = {Real(0), Real(0), Real(0)}, thr[3] = {Real(0), Real(0), Real(0)};
+  double qd[3] = {0.0, 0.0, 0.0};
+  Real mnew[3] = {Real(0), Real(0), Real(0)};
+  if (kFix) {
+    int reach = 1;
+    for (int d = 0; d < DIM; ++d) reach *= L + 3;
+    const double nmax = fmin((double)(sC - sA), (double)reach * (double)A.jb[4 * g + 3]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      thr[c] = Real(2) * Real(A.jb[4 * g + c]);
+      const double jm = fmax(fabs(R.js[0][c]), fabs(R.js[1][c]));
+      const double bnd = nmax * jm * (double)thr[c];
+      if (bnd > 0.0) {
+        qd[c] = bnd / 2145386496.0;  // 2^31 (1 - 2^-10): room for rounding
+        qinv[c] = Real(1.0 / qd[c]);
+      }
+    }
+  }
+
   Real2* P1 = nullptr;
   Real2* P2 = nullptr;
   Real* P3 = nullptr;
@@ -169,6 +212,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     F6 = reinterpret_cast<Real*>(lds);
     Jl = reinterpret_cast<Acc*>(F6 + 6 * fcap);
   }
+  // fixed-point path: Jl holds 3 int windows (each in the space of jcap
+  // doubles), the particle count per cell in the unused half of the first,
+  // and Jo the FP64 windows of the particles above the tile's bounds
+  double* Jo = reinterpret_cast<double*>(Jl) + 3 * jcap;
+  int* Cw = reinterpret_cast<int*>(Jl) + jcap;
 
   // ---- stage E, B on the window; clear the current tile ------------------
   const int nfs = fs[0] * fs[1] * fs[2];
@@ -197,9 +245,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int c = 0; c < 6; ++c) F6[c * fcap + li] = Fg[c * NT + gi];
     }
   }
-  for (int i = tid; i < 3 * jcap; i += nth) Jl[i] = Acc(0);
+  for (int i = tid; i < (kFix ? 6 : 3) * jcap; i += nth) reinterpret_cast<double*>(Jl)[i] = 0.0;
   if (tid < 6) sred[tid] = (tid & 1) ? INT_MIN : INT_MAX;
-  if (tid == 6 || tid == 7) sred[tid] = 0;
+  if (tid >= 6 && tid < 12) sred[tid] = 0;
   __syncthreads();
 
   const PBuf<Real> B = A.buf[A.st->parity];
@@ -324,11 +372,15 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (!finite3(n0, n1, n2)) {
       ++nbad;
       // leave the particle where it is; its box entry keeps the window valid
+      int cwi = 0, cws = 1;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         bmin[d] = min(bmin[d], rel[d]);
         bmax[d] = max(bmax[d], rel[d]);
+        cwi += (rel[d] - jo[d]) * cws;
+        cws *= A.jw[d];
       }
+      if (kFix) atomicAdd(Cw + cwi, 1);
       continue;
     }
     u0 = n0;
@@ -414,111 +466,133 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     }
 
     // ---- Esirkepov current into the LDS tile -----------------------------
-    const Real jx = Real(R.js[sp][0]), jy = Real(R.js[sp][1]), jz = Real(R.js[sp][2]);
-    Acc* J0 = Jl;
-    Acc* J1 = Jl + jcap;
-    Acc* J2 = Jl + 2 * jcap;
-    if (DIM == 2) {
-      // Slot L+1 of an axis (and the last prefix face along it) is nonzero
-      // only when the particle's stencil widened along that axis.
-#pragma unroll
-      for (int v = 0; v < NU; ++v) {
-        if (v == L + 1 && !cross[1]) continue;
-        const Real fy = jx * (S0u[1][v] + half * DSu[1][v]);
-        Acc* row = J0 + iu[0] + jwx * (iu[1] + v);
-        Real acc = Real(0);
-#pragma unroll
-        for (int u = 0; u < L; ++u) {
-          acc += DSu[0][u] * fy;
-          lds_add<Acc>(row + u, Acc(acc));
-        }
-        if (cross[0]) lds_add<Acc>(row + L, Acc(acc + DSu[0][L] * fy));
-      }
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        if (u == L + 1 && !cross[0]) continue;
-        const Real fx = jy * (S0u[0][u] + half * DSu[0][u]);
-        Acc* col = J1 + iu[0] + u + jwx * iu[1];
-        Real acc = Real(0);
-#pragma unroll
-        for (int v = 0; v < L; ++v) {
-          acc += DSu[1][v] * fx;
-          lds_add<Acc>(col + jwx * v, Acc(acc));
-        }
-        if (cross[1]) lds_add<Acc>(col + jwx * L, Acc(acc + DSu[1][L] * fx));
-      }
-      const Real vz = jz * vv[2];
-#pragma unroll
-      for (int v = 0; v < NU; ++v) {
-        if (v == L + 1 && !cross[1]) continue;
-        const Real Av = vz * (S0u[1][v] + half * DSu[1][v]);
-        const Real Bv = vz * (half * S0u[1][v] + third * DSu[1][v]);
-        Acc* row = J2 + iu[0] + jwx * (iu[1] + v);
-#pragma unroll
-        for (int u = 0; u <= L; ++u) lds_add<Acc>(row + u, Acc(S0u[0][u] * Av + DSu[0][u] * Bv));
-        if (cross[0]) lds_add<Acc>(row + L + 1, Acc(S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv));
-      }
-    } else {
-      // J1: prefix along x of DS_x * T_yz
-#pragma unroll
-      for (int w = 0; w < NU; ++w) {
+    // sink(c, i, v) adds v to component c at window index i; kx, ky, kz are
+    // the current scales (-Q dx/(Vc dt) per axis, Q c / Vc for J3 in 2D),
+    // multiplied by the tile's fixed-point scale on the fixed-point path.
+    auto deposit = [&](auto sink, const Real kx, const Real ky, const Real kz) {
+      if (DIM == 2) {
+        // Slot L+1 of an axis (and the last prefix face along it) is nonzero
+        // only when the particle's stencil widened along that axis.
 #pragma unroll
         for (int v = 0; v < NU; ++v) {
-          if ((v == L + 1 && !cross[1]) || (w == L + 1 && !cross[2])) continue;
-          const Real tr = S0u[1][v] * (S0u[2][w] + half * DSu[2][w]) +
-                          DSu[1][v] * (half * S0u[2][w] + third * DSu[2][w]);
-          Acc* row = J0 + iu[0] + jwx * (iu[1] + v + jwy * (iu[2] + w));
+          if (v == L + 1 && !cross[1]) continue;
+          const Real fy = kx * (S0u[1][v] + half * DSu[1][v]);
+          const int ro = iu[0] + jwx * (iu[1] + v);
           Real acc = Real(0);
 #pragma unroll
-          for (int u = 0; u <= L; ++u) {
-            acc += DSu[0][u] * tr;
-            if (u < L || cross[0]) lds_add<Acc>(row + u, Acc(jx * acc));
+          for (int u = 0; u < L; ++u) {
+            acc += DSu[0][u] * fy;
+            sink(0, ro + u, acc);
+          }
+          if (cross[0]) sink(0, ro + L, acc + DSu[0][L] * fy);
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          if (u == L + 1 && !cross[0]) continue;
+          const Real fx = ky * (S0u[0][u] + half * DSu[0][u]);
+          const int co = iu[0] + u + jwx * iu[1];
+          Real acc = Real(0);
+#pragma unroll
+          for (int v = 0; v < L; ++v) {
+            acc += DSu[1][v] * fx;
+            sink(1, co + jwx * v, acc);
+          }
+          if (cross[1]) sink(1, co + jwx * L, acc + DSu[1][L] * fx);
+        }
+        const Real vz = kz * vv[2];
+#pragma unroll
+        for (int v = 0; v < NU; ++v) {
+          if (v == L + 1 && !cross[1]) continue;
+          const Real Av = vz * (S0u[1][v] + half * DSu[1][v]);
+          const Real Bv = vz * (half * S0u[1][v] + third * DSu[1][v]);
+          const int ro = iu[0] + jwx * (iu[1] + v);
+#pragma unroll
+          for (int u = 0; u <= L; ++u) sink(2, ro + u, S0u[0][u] * Av + DSu[0][u] * Bv);
+          if (cross[0]) sink(2, ro + L + 1, S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv);
+        }
+      } else {
+        // J1: prefix along x of DS_x * T_yz
+#pragma unroll
+        for (int w = 0; w < NU; ++w) {
+#pragma unroll
+          for (int v = 0; v < NU; ++v) {
+            if ((v == L + 1 && !cross[1]) || (w == L + 1 && !cross[2])) continue;
+            const Real tr = S0u[1][v] * (S0u[2][w] + half * DSu[2][w]) +
+                            DSu[1][v] * (half * S0u[2][w] + third * DSu[2][w]);
+            const int ro = iu[0] + jwx * (iu[1] + v + jwy * (iu[2] + w));
+            Real acc = Real(0);
+#pragma unroll
+            for (int u = 0; u <= L; ++u) {
+              acc += DSu[0][u] * tr;
+              if (u < L || cross[0]) sink(0, ro + u, kx * acc);
+            }
+          }
+        }
+        // J2: prefix along y of DS_y * T_xz
+#pragma unroll
+        for (int w = 0; w < NU; ++w) {
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            if ((u == L + 1 && !cross[0]) || (w == L + 1 && !cross[2])) continue;
+            const Real tr = S0u[0][u] * (S0u[2][w] + half * DSu[2][w]) +
+                            DSu[0][u] * (half * S0u[2][w] + third * DSu[2][w]);
+            const int co = iu[0] + u + jwx * (iu[1] + jwy * (iu[2] + w));
+            Real acc = Real(0);
+#pragma unroll
+            for (int v = 0; v <= L; ++v) {
+              acc += DSu[1][v] * tr;
+              if (v < L || cross[1]) sink(1, co + jwx * v, ky * acc);
+            }
+          }
+        }
+        // J3: prefix along z of DS_z * T_xy
+#pragma unroll
+        for (int v = 0; v < NU; ++v) {
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            if ((u == L + 1 && !cross[0]) || (v == L + 1 && !cross[1])) continue;
+            const Real tr = S0u[0][u] * (S0u[1][v] + half * DSu[1][v]) +
+                            DSu[0][u] * (half * S0u[1][v] + third * DSu[1][v]);
+            const int co = iu[0] + u + jwx * (iu[1] + v + jwy * iu[2]);
+            Real acc = Real(0);
+#pragma unroll
+            for (int w = 0; w <= L; ++w) {
+              acc += DSu[2][w] * tr;
+              if (w < L || cross[2]) sink(2, co + jwx * jwy * w, kz * acc);
+            }
           }
         }
       }
-      // J2: prefix along y of DS_y * T_xz
-#pragma unroll
-      for (int w = 0; w < NU; ++w) {
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          if ((u == L + 1 && !cross[0]) || (w == L + 1 && !cross[2])) continue;
-          const Real tr = S0u[0][u] * (S0u[2][w] + half * DSu[2][w]) +
-                          DSu[0][u] * (half * S0u[2][w] + third * DSu[2][w]);
-          Acc* col = J1 + iu[0] + u + jwx * (iu[1] + jwy * (iu[2] + w));
-          Real acc = Real(0);
-#pragma unroll
-          for (int v = 0; v <= L; ++v) {
-            acc += DSu[1][v] * tr;
-            if (v < L || cross[1]) lds_add<Acc>(col + jwx * v, Acc(jy * acc));
-          }
-        }
-      }
-      // J3: prefix along z of DS_z * T_xy
-#pragma unroll
-      for (int v = 0; v < NU; ++v) {
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          if ((u == L + 1 && !cross[0]) || (v == L + 1 && !cross[1])) continue;
-          const Real tr = S0u[0][u] * (S0u[1][v] + half * DSu[1][v]) +
-                          DSu[0][u] * (half * S0u[1][v] + third * DSu[1][v]);
-          Acc* col = J2 + iu[0] + u + jwx * (iu[1] + v + jwy * iu[2]);
-          Real acc = Real(0);
-#pragma unroll
-          for (int w = 0; w <= L; ++w) {
-            acc += DSu[2][w] * tr;
-            if (w < L || cross[2]) lds_add<Acc>(col + jwx * jwy * w, Acc(jz * acc));
-          }
-        }
+    };
+    const Real jx = Real(R.js[sp][0]), jy = Real(R.js[sp][1]), jz = Real(R.js[sp][2]);
+    if (!kFix) {
+      deposit([&](int c, int i, Real v) { lds_add<Acc>(Jl + c * jcap + i, Acc(v)); }, jx, jy, jz);
+    } else {
+      // a particle whose step (or |v3|) exceeds the tile's bound takes the
+      // FP64 global path, so that no fixed-point node sum can overflow
+      const Real m0 = fabs(dd[0]), m1 = fabs(dd[1]), m2 = (DIM == 2) ? fabs(vv[2]) : fabs(dd[2]);
+      mnew[0] = fmax(mnew[0], m0);
+      mnew[1] = fmax(mnew[1], m1);
+      mnew[2] = fmax(mnew[2], m2);
+      if (m0 <= thr[0] && m1 <= thr[1] && m2 <= thr[2]) {
+        deposit([&](int c, int i, Real v) { lds_addq(reinterpret_cast<int*>(Jl + c * jcap) + i, v); },
+                jx * qinv[0], jy * qinv[1], jz * qinv[2]);
+      } else {
+        deposit([&](int c, int i, Real v) { lds_add<double>(Jo + c * jcap + i, (double)v); }, jx, jy, jz);
       }
     }
 
     // ---- store, box --------------------------------------------------------
+    int cwi = 0, cws = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int rn = rel[d] + (cn[d] - c[d]);
       bmin[d] = min(bmin[d], rn);
       bmax[d] = max(bmax[d], rn);
+      cwi += (rn - jo[d]) * cws;
+      cws *= A.jw[d];
     }
+    if (kFix) atomicAdd(Cw + cwi, 1);
     if (P::kAbs) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) B.pos[d][p] = xw[d];
@@ -552,6 +626,10 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   for (int off = 32; off >= 1; off >>= 1) {
     nbad += __shfl_xor(nbad, off);
     noor += __shfl_xor(noor, off);
+    if (kFix) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mnew[c] = fmax(mnew[c], __shfl_xor(mnew[c], off));
+    }
   }
   if ((tid & 63) == 0) {
 #pragma unroll
@@ -561,8 +639,21 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     }
     if (nbad) atomicAdd(&sred[6], nbad);
     if (noor) atomicAdd(&sred[7], noor);
+    if (kFix) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) atomicMax(&sred[8 + c], __float_as_int((float)mnew[c]));
+    }
   }
   __syncthreads();
+  if (kFix) {
+    // largest particle count of one cell at the new positions (particles
+    // left in place by a non-finite push are counted at their cell)
+    int cm = 0;
+    for (int i = tid; i < jcap; i += nth) cm = max(cm, Cw[i]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cm = max(cm, __shfl_xor(cm, off));
+    if ((tid & 63) == 0) atomicMax(&sred[11], cm);
+  }
 
   // ---- flush the current tile ------------------------------------------------
   double* Jg = A.J + R.cell0;
@@ -579,11 +670,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     const int li = w0 + jwx * (w1 + jwy * w2);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const Acc v = Jl[c * jcap + li];
-      if (v != Acc(0)) unsafeAtomicAdd(Jg + c * NT + gi, (double)v);
+      const double v = kFix ? (double)reinterpret_cast<const int*>(Jl + c * jcap)[li] * qd[c] + Jo[c * jcap + li]
+                            : (double)Jl[c * jcap + li];
+      if (v != 0.0) unsafeAtomicAdd(Jg + c * NT + gi, v);
     }
   }
 
+  if (kFix) __syncthreads();
   if (tid == 0) {
     bool need = false;
     for (int d = 0; d < 3; ++d) {
@@ -606,6 +699,10 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       A.bbox[g * 6 + 2 * d + 1] = hi;
     }
     if (need) atomicOr(&A.st->sort_request, 1);
+    if (kFix) {
+      for (int c = 0; c < 3; ++c) A.jb[4 * g + c] = __int_as_float(sred[8 + c]);
+      A.jb[4 * g + 3] = (float)sred[11];
+    }
     if (sred[6]) atomicAdd(&A.st->n_nonfinite, (unsigned long long)sred[6]);
     if (sred[7]) atomicAdd(&A.st->n_out_of_range, (unsigned long long)sred[7]);
   }
@@ -618,7 +715,7 @@ __global__ void __launch_bounds__(gpd_block<DIM>())
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
                const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
-  __shared__ int sred[8];
+  __shared__ int sred[12];
   __shared__ int next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(&A.st->tile_queue, 1);

@@ -24,6 +24,7 @@ struct SortArgs {
   int* seg;           // nkeys + 1
   int* keys;          // np_total
   int* bbox;          // 6 G
+  float* jb;          // 4 G: per-tile current bounds and cell counts, set from the sorted particles
   const int* tile_run;
 };
 

@@ -47,7 +47,7 @@ struct Layout {
   size_t p_cell[2], p_pos[2][3], p_u[2][3], p_tag[2];
   // fields / current: component-major
   // scratch
-  size_t s_state, s_runs, s_tile_run, s_counts, s_cursor, s_seg, s_bbox, s_keys, s_blk_run, s_blk_first, s_acc,
+  size_t s_state, s_runs, s_tile_run, s_counts, s_cursor, s_seg, s_bbox, s_jb, s_keys, s_blk_run, s_blk_first, s_acc,
       s_rho;
   long long gmax;
   long long nblocks;
@@ -166,6 +166,8 @@ Layout make_layout(const pic_run_desc* runs, int n_runs) {
   off += align_up(4 * (2 * gmax + 1));
   L.s_bbox = off;
   off += align_up(4 * 6 * gmax);
+  L.s_jb = off;
+  off += align_up(4 * 4 * gmax);
   L.s_keys = off;
   off += align_up(4 * np);
   L.s_blk_run = off;
@@ -376,7 +378,9 @@ pic_status apply_tiling(pic_ctx* c) {
   const size_t fcap = (size_t)c->fw[0] * c->fw[1] * c->fw[2];
   const size_t jcap = (size_t)c->jw[0] * c->jw[1] * c->jw[2];
   const size_t rs = sizeof(Real);
-  c->lds = 6 * rs * fcap + 3 * sizeof(double) * jcap;
+  // FP32: fixed-point current windows plus FP64 windows for particles above
+  // the tile's bounds; FP64: FP64 current windows
+  c->lds = 6 * rs * fcap + (c->f64() ? 3 : 6) * sizeof(double) * jcap;
   if (c->lds > (size_t)c->lds_budget) return c->fail(PIC_ERR_ARG, "tile and margin need more LDS than the workgroup budget");
   // device tables
   c->tile_run_host.assign(G, 0);
@@ -419,6 +423,7 @@ GpdArgs<Real> gpd_args(pic_ctx* c) {
   a.tile_run = reinterpret_cast<const int*>(c->S + c->lay.s_tile_run);
   a.seg = reinterpret_cast<const int*>(c->S + c->lay.s_seg);
   a.bbox = reinterpret_cast<int*>(c->S + c->lay.s_bbox);
+  a.jb = reinterpret_cast<float*>(c->S + c->lay.s_jb);
   a.st = c->state();
   a.buf[0] = c->pbuf<Real>(0);
   a.buf[1] = c->pbuf<Real>(1);
@@ -455,6 +460,7 @@ SortArgs<Real> sort_args(pic_ctx* c) {
   a.seg = reinterpret_cast<int*>(c->S + c->lay.s_seg);
   a.keys = reinterpret_cast<int*>(c->S + c->lay.s_keys);
   a.bbox = reinterpret_cast<int*>(c->S + c->lay.s_bbox);
+  a.jb = reinterpret_cast<float*>(c->S + c->lay.s_jb);
   a.tile_run = reinterpret_cast<const int*>(c->S + c->lay.s_tile_run);
   return a;
 }

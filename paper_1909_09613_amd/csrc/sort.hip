@@ -134,7 +134,9 @@ __global__ void sort_scan(SortArgs<Real> A) {
     base += A.counts[i];
   }
   if (tid == nth - 1) A.seg[A.nkeys] = (int)part[nth - 1];
-  // every tile's particles now lie in its rectangle
+  // every tile's particles now lie in its rectangle; its current bounds are
+  // rebuilt by the arrange pass
+  for (int i = tid; i < 4 * A.G; i += nth) A.jb[i] = 0.0f;
   for (int g = tid; g < A.G; g += nth) {
     const RunDev<Real>& R = A.runs[A.tile_run[g]];
     const int lt = g - R.tile0;
@@ -212,6 +214,7 @@ __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename 
   using Real = typename P::Real;
   if (!A.st->sort_active) return;
   extern __shared__ __align__(16) int sm[];
+  __shared__ int cmax_s;
   const int TC = A.tc, KC = A.kcap;
   int* cnt = sm;                                                // TC: particles per cell
   int* xpre = cnt + TC;                                         // TC + 1: prefix of ranks >= KC
@@ -235,6 +238,7 @@ __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename 
     org[1] = ((lt / R.ntile[0]) % R.ntile[1]) * A.tile[1];
     org[2] = (DIM == 3) ? (lt / (R.ntile[0] * R.ntile[1])) * A.tile[2] : 0;
     for (int i = tid; i < TC; i += kArrangeBlock) cnt[i] = 0;
+    if (tid == 0) cmax_s = 0;
     __syncthreads();
     // rank of each particle within its cell
     for (int i = tid; i < n; i += kArrangeBlock) {
@@ -276,9 +280,19 @@ __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename 
       for (int k = 0; k < KC; ++k) base[k + 1] += base[k];
     }
     __syncthreads();
+    float mb[3] = {0.0f, 0.0f, 0.0f};
     for (int i = tid; i < n; i += kArrangeBlock) {
       const long long q = s0 + (long long)i;
       const int cl = cell_in_tile<P, DIM>(S, q, org, A.tile);
+      if (!P::kAbs) {
+        // bounds of the next step's current contributions (see gpd.hip):
+        // |step| per axis, and |v3| for the out-of-plane current in 2D
+        const float u0 = (float)S.u[0][q], u1 = (float)S.u[1][q], u2 = (float)S.u[2][q];
+        const float ig = 1.0f / sqrtf(1.0f + u0 * u0 + u1 * u1 + u2 * u2);
+        mb[0] = fmaxf(mb[0], (float)R.a[0] * fabsf(u0) * ig);
+        mb[1] = fmaxf(mb[1], (float)R.a[1] * fabsf(u1) * ig);
+        mb[2] = fmaxf(mb[2], (DIM == 2 ? 1.0f : (float)R.a[2]) * fabsf(u2) * ig);
+      }
       const int k = A.keys[q];
       const int slot = (k < KC) ? base[k] + (int)pre[k * TC + cl] : base[KC] + xpre[cl] + (k - KC);
       const long long o = s0 + (long long)slot;
@@ -288,6 +302,20 @@ __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename 
       D.u[1][o] = S.u[1][q];
       D.u[2][o] = S.u[2][q];
       D.tag[o] = S.tag[q];
+    }
+    if (!P::kAbs) {
+      for (int c = 0; c < 3; ++c) {
+        float m = mb[c];
+        for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        if (lane == 0) atomicMax(reinterpret_cast<int*>(A.jb) + 4 * g + c, __float_as_int(m));
+      }
+      // largest particle count of one cell; the two species' maxima add
+      int cm = 0;
+      for (int i = tid; i < TC; i += kArrangeBlock) cm = max(cm, cnt[i]);
+      for (int off = 32; off >= 1; off >>= 1) cm = max(cm, __shfl_xor(cm, off));
+      if (lane == 0) atomicMax(&cmax_s, cm);
+      __syncthreads();
+      if (tid == 0) atomicAdd(A.jb + 4 * g + 3, (float)cmax_s);
     }
     __syncthreads();
   }
