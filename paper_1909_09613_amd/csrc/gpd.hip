@@ -78,13 +78,24 @@ __device__ __forceinline__ void lds_add(Acc* p, Acc v) {
   atomicAdd(p, v);
 }
 
-// Fixed-point LDS accumulation modulo 2^32; v is in units of the tile's
-// quantum and rounded to the nearest integer.
+// Fixed-point LDS accumulation modulo 2^32.  v is in units of the tile's
+// quantum plus one half, so that rounding down (one VALU conversion) rounds
+// the value to the nearest integer.
 __device__ __forceinline__ void lds_addq(int* p, float v) {
-  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)(int)rintf(v));
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)r);
 }
 __device__ __forceinline__ void lds_addq(int* p, double v) {
-  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)(int)rint(v));
+  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)(int)floor(v));
+}
+
+// Keeps a tile-constant integer in a vector register.  The particle loop
+// uses about twenty of them next to the run's tables; left to scalar
+// registers they spill, and each reload costs a vector instruction.
+__device__ __forceinline__ int in_vgpr(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
 }
 
 // m mod n for -2n < m < 2n, without an integer division.  The box keeps
@@ -121,6 +132,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   using Real2 = typename Pair<Real>::T;
   constexpr int NW = L + 1;  // W nodes
   constexpr int NU = L + 2;  // union of old and new form-factor nodes
+  // B-spline tables on the half-integer and the integer lattice: constants
+  constexpr Tab<Real> kWh = make_wtab<Real>(L, 0);
+  constexpr Tab<Real> kWi = make_wtab<Real>(L, 1);
   const int tid = threadIdx.x;
   const int nth = gpd_block<DIM>();
 
@@ -255,6 +269,29 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   int nbad = 0, noor = 0;
   const Real third = Real(1) / Real(3);
   const Real half = Real(0.5);
+  // per-axis constants of the loop: the periodic image of a particle's cell
+  // is rel = wrap(c - co, n) + lo, and it must lie in [rlo, rhi] for the
+  // staged windows; window offsets of the half-lattice, T and union stencils
+  // (kept in vector registers on the FP32 path, where scalar registers run
+  // out; the FP64 path needs its vector registers for its own state)
+  auto pin = [](int x) { return kFix ? in_vgpr(x) : x; };
+  int co[3], lo_[3], nn[3], rlo[3], rhi[3], hoff[3], toff[3], uoff[3], jo_[3], jws[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int n = R.n[d];
+    const int slack = max(0, n - 1 - (bb[2 * d + 1] - bb[2 * d]));
+    const int lo = bb[2 * d] - (slack >> 1);
+    co[d] = pin(org[d] + lo);
+    lo_[d] = pin(lo);
+    nn[d] = pin(n);
+    rlo[d] = pin(max(fo[d] - R.glo[d], jo[d] - R.dlo[d]));
+    rhi[d] = pin(min(fo[d] + fs[d] - 1 - R.ghi[d], jo[d] + jsz[d] - 1 - R.dhi[d]));
+    hoff[d] = pin(R.Wh[d].first - fo[d]);
+    toff[d] = pin(R.T[d].first - fo[d]);
+    uoff[d] = pin(R.Wi[d].first - jo[d]);
+    jo_[d] = pin(jo[d]);
+    jws[d] = pin(d == 0 ? 1 : (d == 1 ? A.jw[0] : A.jw[0] * A.jw[1]));
+  }
 
   for (int p = sA + tid; p < sC; p += nth) {
     const int sp = (p >= sB) ? 1 : 0;
@@ -283,13 +320,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     for (int d = 0; d < DIM; ++d) {
       // periodic image nearest the box: rel in [lo, lo + n), the box centred
       // in that range (a box as wide as the axis starts it)
-      const int n = R.n[d];
-      const int slack = max(0, n - 1 - (bb[2 * d + 1] - bb[2 * d]));
-      const int lo = bb[2 * d] - (slack >> 1);
-      int rr = wrap_near(c[d] - org[d] - lo, n) + lo;
+      const int rr = wrap_near(c[d] - co[d], nn[d]) + lo_[d];
       rel[d] = rr;
-      inwin = inwin && (rr + R.glo[d] >= fo[d]) && (rr + R.ghi[d] < fo[d] + fs[d]) &&
-              (rr + R.dlo[d] >= jo[d]) && (rr + R.dhi[d] < jo[d] + jsz[d]);
+      inwin = inwin && rr >= rlo[d] && rr <= rhi[d];
     }
     if (!inwin) {
       ++noor;
@@ -299,16 +332,24 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     // ---- weights at x^n --------------------------------------------------
     Real wh[3][NW], wt[3][KT];
     int ih[3] = {0, 0, 0}, it[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
+    // FP32 evaluates the B-spline tables from literal constants; FP64 loads
+    // them (64-bit literals would each take registers)
+    auto weights_h = [&](int d, const Tab<Real>& Th) {
       int b;
       Real gg;
-      tab_split(R.Wh[d], c[d], f[d], b, gg);
-      tab_eval<L, NW, false>(R.Wh[d], gg, wh[d]);
-      ih[d] = rel[d] + (b - c[d]) + R.Wh[d].first - fo[d];
+      tab_split(Th, c[d], f[d], b, gg);
+      tab_eval<L, NW, false>(Th, gg, wh[d]);
+      ih[d] = rel[d] + (b - c[d]) + hoff[d];
+    };
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if constexpr (kFix) weights_h(d, kWh);
+      else weights_h(d, R.Wh[d]);
+      int b;
+      Real gg;
       tab_split(R.T[d], c[d], f[d], b, gg);
       tab_eval<L, KT, true>(R.T[d], gg, wt[d]);
-      it[d] = rel[d] + (b - c[d]) + R.T[d].first - fo[d];
+      it[d] = rel[d] + (b - c[d]) + toff[d];
     }
 
     // ---- gather ------------------------------------------------------------
@@ -372,13 +413,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (!finite3(n0, n1, n2)) {
       ++nbad;
       // leave the particle where it is; its box entry keeps the window valid
-      int cwi = 0, cws = 1;
+      int cwi = 0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
         bmin[d] = min(bmin[d], rel[d]);
         bmax[d] = max(bmax[d], rel[d]);
-        cwi += (rel[d] - jo[d]) * cws;
-        cws *= A.jw[d];
+        cwi += (rel[d] - jo_[d]) * jws[d];
       }
       if (kFix) atomicAdd(Cw + cwi, 1);
       continue;
@@ -431,9 +471,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     Real S0u[3][NU], DSu[3][NU];
     int iu[3] = {0, 0, 0};
     bool cross[3] = {false, false, false};  // union stencil one node wider than S0
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const Tab<Real>& Tw = R.Wi[d];
+    auto form_factors = [&](int d, const Tab<Real>& Tw) {
       int b0, b1;
       Real g0, g1;
       tab_split(Tw, c[d], f[d], b0, g0);
@@ -462,14 +500,20 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         S0u[d][k] = a0;
         DSu[d][k] = da + dbv;
       }
-      iu[d] = rel[d] + (min(b0, b1) - c[d]) + Tw.first - jo[d];
+      iu[d] = rel[d] + (min(b0, b1) - c[d]) + uoff[d];
+    };
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if constexpr (kFix) form_factors(d, kWi);
+      else form_factors(d, R.Wi[d]);
     }
 
     // ---- Esirkepov current into the LDS tile -----------------------------
     // sink(c, i, v) adds v to component c at window index i; kx, ky, kz are
     // the current scales (-Q dx/(Vc dt) per axis, Q c / Vc for J3 in 2D),
-    // multiplied by the tile's fixed-point scale on the fixed-point path.
-    auto deposit = [&](auto sink, const Real kx, const Real ky, const Real kz) {
+    // multiplied by the tile's fixed-point scale on the fixed-point path,
+    // and every value carries the offset o (one half there, else zero).
+    auto deposit = [&](auto sink, const Real kx, const Real ky, const Real kz, const Real o) {
       if (DIM == 2) {
         // Slot L+1 of an axis (and the last prefix face along it) is nonzero
         // only when the particle's stencil widened along that axis.
@@ -478,7 +522,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           if (v == L + 1 && !cross[1]) continue;
           const Real fy = kx * (S0u[1][v] + half * DSu[1][v]);
           const int ro = iu[0] + jwx * (iu[1] + v);
-          Real acc = Real(0);
+          Real acc = o;
 #pragma unroll
           for (int u = 0; u < L; ++u) {
             acc += DSu[0][u] * fy;
@@ -491,7 +535,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           if (u == L + 1 && !cross[0]) continue;
           const Real fx = ky * (S0u[0][u] + half * DSu[0][u]);
           const int co = iu[0] + u + jwx * iu[1];
-          Real acc = Real(0);
+          Real acc = o;
 #pragma unroll
           for (int v = 0; v < L; ++v) {
             acc += DSu[1][v] * fx;
@@ -507,8 +551,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           const Real Bv = vz * (half * S0u[1][v] + third * DSu[1][v]);
           const int ro = iu[0] + jwx * (iu[1] + v);
 #pragma unroll
-          for (int u = 0; u <= L; ++u) sink(2, ro + u, S0u[0][u] * Av + DSu[0][u] * Bv);
-          if (cross[0]) sink(2, ro + L + 1, S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv);
+          for (int u = 0; u <= L; ++u)
+            sink(2, ro + u, kFix ? fma(S0u[0][u], Av, fma(DSu[0][u], Bv, o)) : S0u[0][u] * Av + DSu[0][u] * Bv);
+          if (cross[0])
+            sink(2, ro + L + 1, kFix ? fma(S0u[0][L + 1], Av, fma(DSu[0][L + 1], Bv, o))
+                                     : S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv);
         }
       } else {
         // J1: prefix along x of DS_x * T_yz
@@ -524,7 +571,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
             for (int u = 0; u <= L; ++u) {
               acc += DSu[0][u] * tr;
-              if (u < L || cross[0]) sink(0, ro + u, kx * acc);
+              if (u < L || cross[0]) sink(0, ro + u, kFix ? fma(kx, acc, o) : kx * acc);
             }
           }
         }
@@ -541,7 +588,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
             for (int v = 0; v <= L; ++v) {
               acc += DSu[1][v] * tr;
-              if (v < L || cross[1]) sink(1, co + jwx * v, ky * acc);
+              if (v < L || cross[1]) sink(1, co + jwx * v, kFix ? fma(ky, acc, o) : ky * acc);
             }
           }
         }
@@ -558,7 +605,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
             for (int w = 0; w <= L; ++w) {
               acc += DSu[2][w] * tr;
-              if (w < L || cross[2]) sink(2, co + jwx * jwy * w, kz * acc);
+              if (w < L || cross[2]) sink(2, co + jwx * jwy * w, kFix ? fma(kz, acc, o) : kz * acc);
             }
           }
         }
@@ -566,7 +613,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     };
     const Real jx = Real(R.js[sp][0]), jy = Real(R.js[sp][1]), jz = Real(R.js[sp][2]);
     if (!kFix) {
-      deposit([&](int c, int i, Real v) { lds_add<Acc>(Jl + c * jcap + i, Acc(v)); }, jx, jy, jz);
+      deposit([&](int c, int i, Real v) { lds_add<Acc>(Jl + c * jcap + i, Acc(v)); }, jx, jy, jz, Real(0));
     } else {
       // a particle whose step (or |v3|) exceeds the tile's bound takes the
       // FP64 global path, so that no fixed-point node sum can overflow
@@ -576,21 +623,20 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       mnew[2] = fmax(mnew[2], m2);
       if (m0 <= thr[0] && m1 <= thr[1] && m2 <= thr[2]) {
         deposit([&](int c, int i, Real v) { lds_addq(reinterpret_cast<int*>(Jl + c * jcap) + i, v); },
-                jx * qinv[0], jy * qinv[1], jz * qinv[2]);
+                jx * qinv[0], jy * qinv[1], jz * qinv[2], half);
       } else {
-        deposit([&](int c, int i, Real v) { lds_add<double>(Jo + c * jcap + i, (double)v); }, jx, jy, jz);
+        deposit([&](int c, int i, Real v) { lds_add<double>(Jo + c * jcap + i, (double)v); }, jx, jy, jz, Real(0));
       }
     }
 
     // ---- store, box --------------------------------------------------------
-    int cwi = 0, cws = 1;
+    int cwi = 0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int rn = rel[d] + (cn[d] - c[d]);
       bmin[d] = min(bmin[d], rn);
       bmax[d] = max(bmax[d], rn);
-      cwi += (rn - jo[d]) * cws;
-      cws *= A.jw[d];
+      cwi += (rn - jo_[d]) * jws[d];
     }
     if (kFix) atomicAdd(Cw + cwi, 1);
     if (P::kAbs) {

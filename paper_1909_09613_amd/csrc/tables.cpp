@@ -47,6 +47,11 @@ bool build_table(int l, int kind, double a_in, Tab<double>& out, const char** er
     if (err) *err = kBadA;
     return false;
   }
+  if (kind <= 1) {
+    // B-spline tables: the compile-time construction the kernels use
+    out = make_wtab<double>(l, kind);
+    return true;
+  }
   long double fact = 1.0L;
   for (int i = 2; i <= l; ++i) fact *= i;
 

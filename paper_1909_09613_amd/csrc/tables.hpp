@@ -90,6 +90,56 @@ __host__ __device__ inline void tab_diff(const Tab<Real>& t, Real g, Real e, Rea
   }
 }
 
+// The B-spline tables (kinds 0 and 1 below) depend only on l and the
+// lattice, so they are built at compile time: the same truncated-power
+// expansion as build_table, in double (every quantity is a small rational).
+// The particle kernel uses them as literal constants.
+constexpr double cx_binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+constexpr double cx_frac(double x) {
+  long long i = (long long)x;
+  double f = x - (double)i;
+  return f < 0.0 ? f + 1.0 : f;
+}
+template <class Real>
+constexpr Tab<Real> make_wtab(int l, int kind) {
+  Tab<Real> out{};
+  double fact = 1.0;
+  for (int i = 2; i <= l; ++i) fact *= i;
+  const double lam = (kind == 0) ? 0.5 : 0.0;
+  const double sigma = cx_frac(lam - 0.5 * (l + 1));
+  const double first_f = sigma - lam - 0.5 * (l - 1);
+  const int first = (int)(first_f < 0.0 ? first_f - 0.5 : first_f + 0.5);
+  const int K = l + 1;
+  const double D = sigma - first - lam;
+  double c[kMaxNodes][kMaxCoef] = {};
+  for (int k = 0; k < K; ++k)
+    for (int j = 0; j <= l + 1; ++j) {
+      const double beta = ((j & 1) ? -1.0 : 1.0) * cx_binom(l + 1, j) / fact;
+      const double kp = (j - 0.5 * (l + 1)) + k - D;  // knot in g
+      if (kp <= 1e-12) {
+        for (int r = 0; r <= l; ++r) {
+          double p = 1.0;
+          for (int q = 0; q < l - r; ++q) p *= -kp;
+          c[k][r] += beta * cx_binom(l, r) * p;
+        }
+      }
+    }
+  out.sigma = Real(sigma);
+  out.one_minus_sigma = Real(1.0 - sigma);
+  out.kappa = Real(2.0);
+  out.first = first;
+  out.K = K;
+  for (int k = 0; k < kMaxNodes; ++k) {
+    for (int r = 0; r < kMaxCoef; ++r) out.c[k][r] = Real(c[k][r]);
+    out.alpha[k] = Real(0);
+  }
+  return out;
+}
+
 // Host: build the table of one kernel kind for order l.
 //   kind 0: W_l on the half-integer lattice (nodes at m + 1/2)
 //   kind 1: W_l on the integer lattice
