@@ -1,13 +1,16 @@
 """Throughput of the WT gather + push + deposit step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed32|fp64]
+                    [--config 2|3|4|5]
 
-Workload: 2D periodic 1024 x 512 Yee grid, electron-positron pair plasma
-drifting along +x1 with gamma 50, thermal spread u_th = 0.01, 16 particles per
-cell per species (16.8M particles), cubic B-spline (l = 3), WT interpolation
-at c dt = 0.45 dx, synthetic seeded inputs (the paper's Table 1 recipe at
-this size).  A step is one full PIC step: re-sort check, gather + Boris +
-Esirkepov deposit (one kernel), Yee field update.
+Workload (default, --config 2): 2D periodic 1024 x 512 Yee grid,
+electron-positron pair plasma drifting along +x1 with gamma 50, thermal
+spread u_th = 0.01, 16 particles per cell per species (16.8M particles),
+cubic B-spline (l = 3), WT interpolation at c dt = 0.45 dx, synthetic seeded
+inputs (the paper's Table 1 recipe at this size).  --config 3, 4, 5 run the
+3D 256x128x128 workload, the 64-run batched Courant sweep and the 2D
+4096x2048 workload instead.  A step is one full PIC step: re-sort check,
+gather + Boris + Esirkepov deposit (one kernel), Yee field update.
 
 Prints one JSON line.  `value` is particle-steps per second of the whole job
 over the K timed steps (inputs resident in HBM).  `roofline` refers to the
@@ -33,6 +36,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+WORKLOADS = {
+    2: "2D periodic 1024x512, drifting pair plasma gamma 50, u_th 0.01, 16 ppc/species, "
+       "cubic B-spline, WT at c dt = 0.45 dx",
+    3: "3D periodic 256x128x128, drifting pair plasma gamma 50, u_th 0.01, 8 ppc/species, "
+       "quadratic B-spline, WT at c dt = 0.5 dx",
+    4: "64 batched 2D periodic runs, grids U{128..512} x U{64..256}, c dt/dx = 0.1 + 0.6 r/63, "
+       "gamma 10/50/100, u_th 0.01, 8 ppc/species, quadratic B-spline, WT",
+    5: "2D periodic 4096x2048, drifting pair plasma gamma 100, u_th 0.01, 16 ppc/species, "
+       "cubic B-spline, WT at c dt = 0.3 dx",
+}
 
 
 def particle_bytes(ndim, precision):
@@ -102,6 +116,7 @@ def main():
     ap.add_argument("--precision", default="mixed32", choices=["mixed32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--tile", default=None, help="tile shape, e.g. 32x16")
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5], help="workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -115,16 +130,18 @@ def main():
     import paper_1909_09613_amd as wt
     from paper_1909_09613_amd import inputs
 
-    spec = inputs.config(2)[0]
+    specs = inputs.config(args.config)
+    spec = specs[0]
     prec = wt.PIC_FP64 if args.precision == "fp64" else wt.PIC_MIXED32
     t_setup = time.perf_counter()
-    species = inputs.make_species(spec)
-    sim = wt.Sim([spec], prec)
+    sim = wt.Sim(specs, prec)
     if args.tile:
         t = [int(v) for v in args.tile.split("x")] + [0]
         wt.pic_set_tiling(sim.ctx, tuple(t[:3]), 0, 0)
-    sim.set_species(0, species)
-    np_total = 2 * spec.ncell * spec.ppc_s
+    for r, sr in enumerate(specs):
+        sim.set_species(r, inputs.make_species(sr))
+    np_total = sum(2 * sr.ncell * sr.ppc_s for sr in specs)
+    ncell_total = sum(sr.ncell for sr in specs)
     print("setup %.1f s, %d particles" % (time.perf_counter() - t_setup, np_total), file=sys.stderr, flush=True)
 
     if args.calibrate_copy:
@@ -136,8 +153,20 @@ def main():
         sim.synchronize()
         del src, dst
 
-    # warmup: the first sort, then enough steps that the step graph is
-    # captured and replayed at least once before anything is timed
+    # the first step sorts every particle (set-up order): timed on its own
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sim.stream):
+        start.record(sim.stream)
+        sim.gpd()
+        stop.record(sim.stream)
+    stop.synchronize()
+    ms_sort_step = start.elapsed_time(stop)
+    sim.field_update()
+
+    # warmup: enough steps that the step graph is captured and replayed at
+    # least once before anything is timed
     sim.step(max(args.warmup, 1))
     sim.step(16)
     sim.synchronize()
@@ -145,8 +174,7 @@ def main():
     # timed region: eager steps with the library's per-launch kernel events
     wt.pic_kernel_timing(sim.ctx, True)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    d0 = sim.diagnostics(0)
     with torch.cuda.stream(sim.stream):
         start.record(sim.stream)
         for _ in range(args.steps):
@@ -173,16 +201,18 @@ def main():
     ms_step = ms_total / args.steps
     value = np_total * args.steps / (ms_total / 1e3)
     prec_name = args.precision
-    alg_bytes = np_total * particle_bytes(spec.ndim, prec_name) + spec.ncell * cell_bytes(prec_name)
+    alg_bytes = np_total * particle_bytes(spec.ndim, prec_name) + ncell_total * cell_bytes(prec_name)
     achieved = alg_bytes / (gpd_ms / 1e3) / 1e9
     digest = source_digest()
-    traffic = load_traffic(prec_name, digest)
+    traffic = load_traffic(prec_name, digest) if args.config == 2 else None
 
     if not args.no_cpu:
         rng = np.random.default_rng(0)
         E = inputs.random_fields(rng, spec.ncell, 1e-3)
         B = inputs.random_fields(rng, spec.ncell, 1e-3)
         cpu = cpu_baseline(spec, inputs.make_species(spec), E, B)
+        if len(specs) > 1:
+            cpu["sample"] += " (first run of the batch)"
     else:
         cpu = None
 
@@ -200,8 +230,7 @@ def main():
         "dtype": "f32" if prec_name == "mixed32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "2D periodic 1024x512, drifting pair plasma gamma 50, u_th 0.01, 16 ppc/species, "
-                        "cubic B-spline, WT at c dt = 0.45 dx",
+            "workload": WORKLOADS[args.config],
             "particles": np_total, "precision": prec_name,
         },
         "roofline": {
@@ -211,6 +240,12 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes, "source_digest": digest,
         },
         "graph_ms_per_step": ms_graph / args.steps,
+        "breakdown": {
+            "gpd_kernel_ms": gpd_ms,
+            "rest_of_step_ms": ms_step - gpd_ms,
+            "first_step_with_full_sort_ms": ms_sort_step,
+            "sorts_in_timed_region": d.n_sorts - d0.n_sorts,
+        },
         "cpu_baseline": cpu,
         "check": {"n_nonfinite": d.n_nonfinite, "n_out_of_range": d.n_out_of_range, "n_sorts": d.n_sorts,
                   "field_energy": sum(d.UE) + sum(d.UB)},

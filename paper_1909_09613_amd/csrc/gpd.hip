@@ -190,7 +190,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // stored velocities after a sort) give a node value below 2^31 quanta;
   // the sums are taken modulo 2^32, so only the final value must fit.  A
   // particle above a threshold deposits into FP64 LDS windows instead.
-  constexpr bool kFix = !P::kAbs;
+  // (2D only: the 3D windows are large enough that the extra FP64 windows
+  // would force smaller tiles; 3D accumulates in FP64 at both precisions)
+  constexpr bool kFix = !P::kAbs && DIM == 2;
   Real qinv[3] = {Real(0), Real(0), Real(0)}, thr[3] = {Real(0), Real(0), Real(0)};
   double qd[3] = {0.0, 0.0, 0.0};
   Real mnew[3] = {Real(0), Real(0), Real(0)};
@@ -274,7 +276,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // staged windows; window offsets of the half-lattice, T and union stencils
   // (kept in vector registers on the FP32 path, where scalar registers run
   // out; the FP64 path needs its vector registers for its own state)
-  auto pin = [](int x) { return kFix ? in_vgpr(x) : x; };
+  auto pin = [](int x) { return P::kAbs ? x : in_vgpr(x); };
   int co[3], lo_[3], nn[3], rlo[3], rhi[3], hoff[3], toff[3], uoff[3], jo_[3], jws[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
