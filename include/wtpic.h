@@ -155,6 +155,15 @@ pic_status pic_field_update(pic_ctx *ctx);
  * from a captured HIP graph of the step sequence.  Asynchronous. */
 pic_status pic_step(pic_ctx *ctx, int32_t n_steps);
 
+/* n_steps full steps with the diagnostics of one run recorded every
+ * diag_every steps (Sec. 3 follows the field energy over time): history[i]
+ * receives pic_diagnostics after step (i + 1) * diag_every, for
+ * i < n_steps / diag_every; host array of that many pic_diag, owned by the
+ * caller.  Synchronises the stream at each record.  PIC_ERR_ARG if
+ * diag_every < 1 or history is NULL; PIC_ERR_NUMERIC as pic_diagnostics
+ * (the history up to that record is filled). */
+pic_status pic_step_diag(pic_ctx *ctx, int32_t n_steps, int32_t diag_every, int32_t run, pic_diag *history);
+
 /* FP64 device reductions for one run (energies, momentum, Gauss residual,
  * error counters), copied to *out.  Synchronises the stream.  Returns
  * PIC_ERR_NUMERIC if the error counters are nonzero (out is still filled). */

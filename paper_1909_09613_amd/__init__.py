@@ -29,7 +29,8 @@ STATUS_NAMES = {
 
 EXPORTED = [
     "pic_query_layout", "pic_init", "pic_set_particles", "pic_get_particles", "pic_set_fields",
-    "pic_get_fields", "pic_gather_push_deposit", "pic_field_update", "pic_step", "pic_diagnostics",
+    "pic_get_fields", "pic_gather_push_deposit", "pic_field_update", "pic_step", "pic_step_diag",
+    "pic_diagnostics",
     "pic_set_tiling", "pic_kernel_timing", "pic_last_error", "pic_destroy", "pic_table_weights",
 ]
 
@@ -97,6 +98,7 @@ def lib():
             "pic_gather_push_deposit": [vp],
             "pic_field_update": [vp],
             "pic_step": [vp, i32],
+            "pic_step_diag": [vp, i32, i32, i32, ctypes.POINTER(pic_diag)],
             "pic_diagnostics": [vp, i32, ctypes.POINTER(pic_diag)],
             "pic_set_tiling": [vp, ctypes.POINTER(i32), i32, i32],
             "pic_kernel_timing": [vp, i32, dp, ctypes.POINTER(i64)],
@@ -199,6 +201,14 @@ def pic_step(ctx, n_steps):
     _check(lib().pic_step(ctx, n_steps), ctx)
 
 
+def pic_step_diag(ctx, n_steps, diag_every, run):
+    """n_steps steps; the diagnostics of `run` every diag_every steps."""
+    n = n_steps // diag_every if diag_every > 0 else 0
+    hist = (pic_diag * max(n, 1))()
+    _check(lib().pic_step_diag(ctx, n_steps, diag_every, run, hist), ctx)
+    return [hist[i] for i in range(n)]
+
+
 def pic_diagnostics(ctx, run, allow_numeric=False):
     d = pic_diag()
     st = lib().pic_diagnostics(ctx, run, ctypes.byref(d))
@@ -286,6 +296,9 @@ class Sim:
 
     def step(self, n=1):
         pic_step(self.ctx, n)
+
+    def step_diag(self, n, every, run=0):
+        return pic_step_diag(self.ctx, n, every, run)
 
     def diagnostics(self, run=0, allow_numeric=False):
         return pic_diagnostics(self.ctx, run, allow_numeric)

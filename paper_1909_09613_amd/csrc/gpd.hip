@@ -482,6 +482,22 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       tab_eval<L, NW, false>(Tw, g0, s0);
       const int db = b1 - b0;
       cross[d] = db != 0;
+      const bool shA = db < 0, shB = db > 0;
+      if (__all(fabs(dd[d]) >= Real(0.0625))) {
+        // every step of the wave is long: S1 - S0 directly keeps its
+        // precision (rounding of order one against |step| >= 1/16)
+        Real s1[NW];
+        tab_eval<L, NW, false>(Tw, g1, s1);
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+          const Real a0 = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));
+          const Real a1 = shB ? (k >= 1 ? s1[k - 1] : Real(0)) : (k < NW ? s1[k] : Real(0));
+          S0u[d][k] = a0;
+          DSu[d][k] = a1 - a0;
+        }
+        iu[d] = rel[d] + (min(b0, b1) - c[d]) + uoff[d];
+        return;
+      }
       const Real eA = (db == 0) ? g1 : (db > 0 ? Real(1) : Real(0));
       const Real lA = (db == 0) ? dd[d] : (db > 0 ? Real(1) - g0 : -g0);
       tab_diff<L>(Tw, g0, eA, lA, dA);
@@ -493,7 +509,6 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
         for (int k = 0; k < NW; ++k) dB[k] = Real(0);
       }
-      const bool shA = db < 0, shB = db > 0;
 #pragma unroll
       for (int k = 0; k < NU; ++k) {
         const Real a0 = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));

@@ -971,6 +971,18 @@ pic_status pic_step(pic_ctx* c, int32_t n_steps) {
 }
 
 
+pic_status pic_step_diag(pic_ctx* c, int32_t n_steps, int32_t diag_every, int32_t run, pic_diag* history) {
+  if (!c) return PIC_ERR_ARG;
+  if (diag_every < 1 || n_steps < 0 || !history) return c->fail(PIC_ERR_ARG, "diag_every >= 1, n_steps >= 0, history != NULL");
+  if (run < 0 || run >= c->nruns) return c->fail(PIC_ERR_ARG, "bad run");
+  for (int32_t i = 0; i < n_steps / diag_every; ++i) {
+    pic_status st = pic_step(c, diag_every);
+    if (st == PIC_OK) st = pic_diagnostics(c, run, &history[i]);
+    if (st != PIC_OK) return st;
+  }
+  return pic_step(c, n_steps % diag_every);
+}
+
 pic_status pic_diagnostics(pic_ctx* c, int32_t run, pic_diag* out) {
   if (!c) return PIC_ERR_ARG;
   if (run < 0 || run >= c->nruns || !out) return c->fail(PIC_ERR_ARG, "bad run or NULL out");

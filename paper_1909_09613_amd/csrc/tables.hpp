@@ -33,7 +33,10 @@ struct Tab {
 // Split a position given as (cell, in-cell offset f in [0,1)) for a table.
 template <class Real>
 __host__ __device__ inline void tab_split(const Tab<Real>& t, int cell, Real f, int& base, Real& g) {
-  if (f >= t.sigma) {
+  if (t.sigma == Real(0)) {  // no split (folds away for constant tables)
+    base = cell;
+    g = f;
+  } else if (f >= t.sigma) {
     base = cell;
     g = f - t.sigma;
   } else {

@@ -285,6 +285,36 @@ def test_step_graph_matches_eager(orc):
     assert np.max(np.abs(Ea - Eb)) <= 1e-12 * max(1.0, np.max(np.abs(Eb)))
 
 
+def test_step_diag_history():
+    """pic_step_diag records the same diagnostics as stepping in chunks and
+    calling pic_diagnostics after each; a step count that is not a multiple
+    of the record interval ends with the remaining steps."""
+    spec = RunSpec(2, (40, 32), 2, 0.45, 50.0, 0.01, 2, 62)
+    sp = inputs.make_species(spec)
+    a = wt.Sim([spec], wt.PIC_FP64)
+    b = wt.Sim([spec], wt.PIC_FP64)
+    try:
+        a.set_species(0, sp)
+        b.set_species(0, sp)
+        hist = a.step_diag(23, 5)
+        ref = []
+        for _ in range(4):
+            b.step(5)
+            ref.append(b.diagnostics(0))
+        b.step(3)
+        end_a, end_b = a.diagnostics(0), b.diagnostics(0)
+    finally:
+        a.close()
+        b.close()
+    assert len(hist) == 4
+    for h, r in zip(hist, ref):
+        assert h.step == r.step
+        for k in range(3):
+            assert abs(h.UE[k] - r.UE[k]) <= 1e-9 * max(r.UE[k], 1e-300)
+            assert abs(h.UB[k] - r.UB[k]) <= 1e-9 * max(r.UB[k], 1e-300)
+    assert end_a.step == end_b.step == 23
+
+
 def test_diagnostics_match_oracle(orc):
     spec = RunSpec(2, (32, 24), 3, 0.45, 50.0, 0.01, 2, 71)
     sp, E, B = H.random_state(spec, 3)
