@@ -1,0 +1,136 @@
+"""GPU parity on degenerate particle distributions, one step from identical
+state against the FP64 oracle, with the one-step tolerances:
+
+  * a dense cell: a third of every species in one cell (the sort's arrange
+    pass orders ranks beyond its level cap in cell order, and the
+    fixed-point current's cell-count bound is large);
+  * empty tiles: all particles in the left third of the grid;
+  * positions on cell faces and just below the periodic end, particles at
+    rest, and offsets that round up to the next cell in FP32 (carried into
+    the cell index, as the oracle's quantisation does);
+  * every particle of a species at one point.
+"""
+import numpy as np
+import pytest
+
+import paper_1909_09613_amd as wt
+from paper_1909_09613_amd import inputs
+from paper_1909_09613_amd.inputs import RunSpec
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(orc, spec, sp, precision, seed=3, amp=0.05):
+    fp32 = precision == wt.PIC_MIXED32
+    rng = np.random.default_rng(seed)
+    E = inputs.random_fields(rng, spec.ncell, amp)
+    B = inputs.random_fields(rng, spec.ncell, amp)
+    if fp32:
+        for s in sp:
+            s["x"], s["u"] = inputs.quantize_fp32(s["x"], s["u"])
+        E = E.astype(np.float32).astype(np.float64)
+        B = B.astype(np.float32).astype(np.float64)
+    grids = []
+    for which in (None, 0, 1):
+        g = H.oracle_grid(orc, spec)
+        g.E[:] = E
+        g.B[:] = B
+        g.zero_J()
+        ref = H.copy_species(sp)
+        for k, s in enumerate(ref):
+            if which is None or which == k:
+                g.push_species(s["x"], s["u"], s["qm"], s["Q"])
+        grids.append((g, ref))
+    (g, ref), (ge, _), (gp, _) = grids
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, sp)
+        sim.set_fields(0, E, B)
+        sim.gpd()
+        got = [sim.particles(0, s) for s in range(2)]
+        _, _, J = sim.fields(0)
+        d = sim.diagnostics(0)
+        assert d.n_nonfinite == 0 and d.n_out_of_range == 0
+        # a further step after the arranged sort must stay consistent
+        sim.field_update()
+        sim.gpd()
+        d2 = sim.diagnostics(0)
+        assert d2.n_nonfinite == 0 and d2.n_out_of_range == 0
+    finally:
+        sim.close()
+    ex, eu = H.particle_errors(spec, ref, got)
+    scale = np.max(np.abs(ge.J) + np.abs(gp.J), axis=1)
+    ej = [float(np.max(np.abs(J[k] - g.J[k])) / scale[k]) if scale[k] > 0 else float(np.max(np.abs(J[k])))
+          for k in range(3)]
+    print("edge %s %s: dx=%.2e du=%.2e dJ/scale=%s" % (
+        "fp32" if fp32 else "fp64", spec.n, ex, eu, ["%.2e" % v for v in ej]), flush=True)
+    tol_x = 2e-6 if fp32 else 1e-12
+    assert ex <= tol_x and eu <= tol_x
+    for k in range(3):
+        assert ej[k] <= H.current_tol(spec, k, fp32)
+
+
+def _species(spec, xs):
+    """Species dicts with the given positions and drifting momenta."""
+    rng = np.random.default_rng(spec.seed)
+    out = []
+    for (qm, Q, M), x in zip(spec.species_constants(), xs):
+        u = inputs.drifting_momenta(rng, len(x), spec.gamma0, spec.u_th)
+        out.append({"x": x, "u": u, "qm": qm, "Q": Q, "M": M})
+    return out
+
+
+PRECISIONS = [wt.PIC_FP64, wt.PIC_MIXED32]
+IDS = ["fp64", "fp32"]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS, ids=IDS)
+def test_dense_cell(orc, precision):
+    spec = RunSpec(2, (48, 32), 3, 0.45, 50.0, 0.01, 4, 501)
+    n = spec.ncell * spec.ppc_s
+    xs = []
+    for s in range(2):
+        x = inputs.make_species(spec)[s]["x"].copy()
+        k = n // 3
+        x[:k, 0] = 21.0 + 0.999 * np.random.default_rng(10 + s).random(k)
+        x[:k, 1] = 13.0 + 0.999 * np.random.default_rng(20 + s).random(k)
+        xs.append(x)
+    _run(orc, spec, _species(spec, xs), precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS, ids=IDS)
+def test_empty_tiles(orc, precision):
+    spec = RunSpec(2, (96, 40), 2, 0.3, 50.0, 0.01, 2, 502)
+    n = spec.ncell * spec.ppc_s
+    rng = np.random.default_rng(30)
+    xs = []
+    for s in range(2):
+        x = np.zeros((n, 3))
+        x[:, 0] = rng.random(n) * 30.0
+        x[:, 1] = rng.random(n) * 40.0
+        xs.append(x)
+    _run(orc, spec, _species(spec, xs), precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS, ids=IDS)
+def test_faces_rest_and_carry(orc, precision):
+    spec = RunSpec(2, (40, 24), 2, 0.5, 20.0, 0.05, 2, 503, colocated=False)
+    sp = inputs.make_species(spec)
+    for s in sp:
+        x, u = s["x"], s["u"]
+        x[0:50, 0] = np.floor(x[0:50, 0])                 # on a cell face along x
+        x[50:100, 1] = np.floor(x[50:100, 1])             # on a cell face along y
+        x[100:120, 0] = spec.n[0] - 2.0 ** -22            # just below the periodic end
+        x[120:140, 1] = spec.n[1] - 2.0 ** -22
+        x[140:160, 0] = np.floor(x[140:160, 0]) + 1.0 - 2.0 ** -30   # rounds up in FP32
+        u[160:200] = 0.0                                  # at rest
+    _run(orc, spec, sp, precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS, ids=IDS)
+def test_all_particles_at_one_point(orc, precision):
+    spec = RunSpec(2, (16, 12), 3, 0.45, 50.0, 0.01, 1, 504)
+    xs = [np.array([[7.3, 4.6, 0.0]] * spec.ncell), np.array([[7.3, 4.6, 0.0]] * spec.ncell)]
+    # every particle of a species at one point: the densest possible cell
+    _run(orc, spec, _species(spec, xs), precision)
