@@ -91,7 +91,8 @@ struct DevState {
   unsigned long long n_nonfinite;
   unsigned long long n_out_of_range;
   unsigned long long n_sorts;
-  unsigned long long pad2;
+  unsigned int groups_done;    // particle-kernel groups that found the queue empty
+  unsigned int pad2;
 };
 
 template <class Real>

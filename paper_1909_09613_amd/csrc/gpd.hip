@@ -772,7 +772,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 }
 
 // Persistent workgroups: each takes tiles from a device queue until none are
-// left, so uneven tiles (edge tiles, runs of different size) balance.
+// left, so uneven tiles (edge tiles, runs of different size) balance.  The
+// queue starts at zero (set at initialisation, then rewound by the last
+// group of every launch).
 template <class P, int L, int DIM>
 __global__ void __launch_bounds__(gpd_block<DIM>())
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
@@ -785,7 +787,15 @@ __global__ void __launch_bounds__(gpd_block<DIM>())
     __syncthreads();
     const int g = next;
     __syncthreads();
-    if (g >= A.G) return;
+    if (g >= A.G) {
+      // the last group to find the queue empty rewinds it for the next
+      // launch (every group has taken its final ticket by then)
+      if (threadIdx.x == 0 && atomicAdd(&A.st->groups_done, 1u) == gridDim.x - 1) {
+        A.st->tile_queue = 0;
+        A.st->groups_done = 0;
+      }
+      return;
+    }
     const int kt = runs[tile_run[g]].KT;
     if (kt == L + 1)
       gpd_tile<P, L, DIM, L + 1>(A, runs, tile_run, g, lds_dyn, sred);
@@ -795,12 +805,9 @@ __global__ void __launch_bounds__(gpd_block<DIM>())
   }
 }
 
-__global__ void gpd_queue_reset(DevState* st) { st->tile_queue = 0; }
-
 template <class P, int L, int DIM>
 static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
   const int grid = a.G < a.max_groups ? a.G : a.max_groups;
-  hipLaunchKernelGGL(gpd_queue_reset, dim3(1), dim3(1), 0, s, a.st);
   hipLaunchKernelGGL((gpd_kernel<P, L, DIM>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs, a.tile_run);
   return hipGetLastError();
 }
