@@ -189,12 +189,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // (thr_c = 2 * the tile's largest m_c of the previous step, or of the
   // stored velocities after a sort) give a node value below 2^31 quanta;
   // the sums are taken modulo 2^32, so only the final value must fit.  A
-  // particle above a threshold deposits into FP64 LDS windows instead.
-  // (2D only: the 3D windows are large enough that the extra FP64 windows
-  // would force smaller tiles; 3D accumulates in FP64 at both precisions)
-  constexpr bool kFix = !P::kAbs && DIM == 2;
+  // particle above a threshold deposits into a second set of fixed-point
+  // windows whose quantum uses the a-priori bound m_c < a_c (|v| < c; 1 for
+  // v3 in 2D), coarse but safe for any particle.
+  constexpr bool kFix = !P::kAbs;
   Real qinv[3] = {Real(0), Real(0), Real(0)}, thr[3] = {Real(0), Real(0), Real(0)};
-  double qd[3] = {0.0, 0.0, 0.0};
+  Real qcinv[3] = {Real(0), Real(0), Real(0)};
+  double qd[3] = {0.0, 0.0, 0.0}, qcd[3] = {0.0, 0.0, 0.0};
   Real mnew[3] = {Real(0), Real(0), Real(0)};
   if (kFix) {
     int reach = 1;
@@ -208,6 +209,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       if (bnd > 0.0) {
         qd[c] = bnd / 2145386496.0;  // 2^31 (1 - 2^-10): room for rounding
         qinv[c] = Real(1.0 / qd[c]);
+      }
+      const double amax = (DIM == 2 && c == 2) ? 1.0 : (double)R.a[c];
+      const double cbnd = nmax * jm * amax;
+      if (cbnd > 0.0) {
+        qcd[c] = cbnd / 2145386496.0;
+        qcinv[c] = Real(1.0 / qcd[c]);
       }
     }
   }
@@ -228,11 +235,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     F6 = reinterpret_cast<Real*>(lds);
     Jl = reinterpret_cast<Acc*>(F6 + 6 * fcap);
   }
-  // fixed-point path: Jl holds 3 int windows (each in the space of jcap
-  // doubles), the particle count per cell in the unused half of the first,
-  // and Jo the FP64 windows of the particles above the tile's bounds
-  double* Jo = reinterpret_cast<double*>(Jl) + 3 * jcap;
-  int* Cw = reinterpret_cast<int*>(Jl) + jcap;
+  // fixed-point path: 3 fine and 3 coarse int windows, then the particle
+  // count per cell
+  int* Qf = reinterpret_cast<int*>(Jl);
+  int* Qc = Qf + 3 * jcap;
+  int* Cw = Qc + 3 * jcap;
 
   // ---- stage E, B on the window; clear the current tile ------------------
   const int nfs = fs[0] * fs[1] * fs[2];
@@ -261,7 +268,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int c = 0; c < 6; ++c) F6[c * fcap + li] = Fg[c * NT + gi];
     }
   }
-  for (int i = tid; i < (kFix ? 6 : 3) * jcap; i += nth) reinterpret_cast<double*>(Jl)[i] = 0.0;
+  if (kFix) {
+    for (int i = tid; i < 7 * jcap; i += nth) Qf[i] = 0;
+  } else {
+    for (int i = tid; i < 3 * jcap; i += nth) Jl[i] = Acc(0);
+  }
   if (tid < 6) sred[tid] = (tid & 1) ? INT_MIN : INT_MAX;
   if (tid >= 6 && tid < 12) sred[tid] = 0;
   __syncthreads();
@@ -639,10 +650,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       mnew[1] = fmax(mnew[1], m1);
       mnew[2] = fmax(mnew[2], m2);
       if (m0 <= thr[0] && m1 <= thr[1] && m2 <= thr[2]) {
-        deposit([&](int c, int i, Real v) { lds_addq(reinterpret_cast<int*>(Jl + c * jcap) + i, v); },
+        deposit([&](int c, int i, Real v) { lds_addq(Qf + c * jcap + i, v); },
                 jx * qinv[0], jy * qinv[1], jz * qinv[2], half);
       } else {
-        deposit([&](int c, int i, Real v) { lds_add<double>(Jo + c * jcap + i, (double)v); }, jx, jy, jz, Real(0));
+        deposit([&](int c, int i, Real v) { lds_addq(Qc + c * jcap + i, v); },
+                jx * qcinv[0], jy * qcinv[1], jz * qcinv[2], half);
       }
     }
 
@@ -733,7 +745,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     const int li = w0 + jwx * (w1 + jwy * w2);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double v = kFix ? (double)reinterpret_cast<const int*>(Jl + c * jcap)[li] * qd[c] + Jo[c * jcap + li]
+      const double v = kFix ? (double)Qf[c * jcap + li] * qd[c] + (double)Qc[c * jcap + li] * qcd[c]
                             : (double)Jl[c * jcap + li];
       if (v != 0.0) unsafeAtomicAdd(Jg + c * NT + gi, v);
     }

@@ -378,9 +378,9 @@ pic_status apply_tiling(pic_ctx* c) {
   const size_t fcap = (size_t)c->fw[0] * c->fw[1] * c->fw[2];
   const size_t jcap = (size_t)c->jw[0] * c->jw[1] * c->jw[2];
   const size_t rs = sizeof(Real);
-  // 2D FP32: fixed-point current windows plus FP64 windows for particles
-  // above the tile's bounds; otherwise FP64 current windows
-  c->lds = 6 * rs * fcap + ((c->f64() || nd == 3) ? 3 : 6) * sizeof(double) * jcap;
+  // FP32: fine and coarse fixed-point current windows and a cell count
+  // (7 ints per node); FP64: FP64 current windows
+  c->lds = 6 * rs * fcap + (c->f64() ? 3 * sizeof(double) : 7 * sizeof(int)) * jcap;
   if (c->lds > (size_t)c->lds_budget) return c->fail(PIC_ERR_ARG, "tile and margin need more LDS than the workgroup budget");
   // device tables
   c->tile_run_host.assign(G, 0);
