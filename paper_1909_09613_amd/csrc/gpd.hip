@@ -326,6 +326,10 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int d = 0; d < DIM; ++d) f[d] = B.pos[d][p];
     }
     Real u0 = B.u[0][p], u1 = B.u[1][p], u2 = B.u[2][p];
+    // all six loads are in flight before anything waits on one of them (left
+    // alone, the compiler sinks the offset and momentum loads below the
+    // window test, a second memory round trip per particle)
+    asm volatile("" ::"v"(u0), "v"(u1), "v"(u2), "v"(f[0]), "v"(f[1]), "v"(f[DIM - 1]), "v"(xo[0]));
 
     int rel[3] = {0, 0, 0};
     bool inwin = true;

@@ -80,11 +80,14 @@ CASES_2D = [
     RunSpec(2, (33, 24), 2, 0.5, 50.0, 0.01, 3, 14),             # MC limit
     RunSpec(2, (30, 26), 3, 0.6, 10.0, 0.1, 2, 15),              # a > 1/2: l+2 T nodes
     RunSpec(2, (32, 32), 2, 0.3, 50.0, 0.01, 3, 16, scheme=1),  # MC scheme
+    # anisotropic cells: c dt/dx = 0.4 along x, 0.533 along y (l+1 and l+2 T nodes)
+    RunSpec(2, (36, 28), 3, 0.4, 50.0, 0.01, 3, 17, dx=(1.0, 0.75, 1.0)),
 ]
 CASES_3D = [
     RunSpec(3, (16, 12, 10), 2, 0.5, 50.0, 0.01, 2, 21),
     RunSpec(3, (14, 12, 11), 1, 0.4, 20.0, 0.05, 2, 22, colocated=False),
     RunSpec(3, (12, 12, 12), 3, 0.35, 50.0, 0.01, 1, 23),
+    RunSpec(3, (14, 12, 10), 2, 0.3, 50.0, 0.01, 2, 24, dx=(1.0, 0.8, 1.25)),  # anisotropic cells
 ]
 
 
@@ -110,10 +113,12 @@ def test_one_step_fp32(orc, spec):
         assert ej[k] <= H.current_tol(spec, k, True)
 
 
-@pytest.mark.parametrize("ndim,solver", [(2, 0), (2, 1), (3, 0), (3, 1)])
+@pytest.mark.parametrize("ndim,solver,aniso", [(2, 0, False), (2, 1, False), (3, 0, False), (3, 1, False),
+                                               (2, 1, True), (3, 1, True)])
 @pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32])
-def test_field_update(orc, ndim, solver, precision):
-    spec = RunSpec(ndim, (20, 17) if ndim == 2 else (12, 10, 9), 2, 0.4, 50.0, 0.01, 1, 31, solver=solver)
+def test_field_update(orc, ndim, solver, aniso, precision):
+    dx = ((1.0, 0.7, 1.0) if ndim == 2 else (1.0, 0.8, 1.25)) if aniso else (1.0, 1.0, 1.0)
+    spec = RunSpec(ndim, (20, 17) if ndim == 2 else (12, 10, 9), 2, 0.4, 50.0, 0.01, 1, 31, solver=solver, dx=dx)
     rng = np.random.default_rng(5)
     E = inputs.random_fields(rng, spec.ncell, 1.0)
     B = inputs.random_fields(rng, spec.ncell, 1.0)

@@ -180,6 +180,22 @@ def test_deposit_discrete_continuity(orc, ndim, l):
 
 
 @pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("l", [1, 3])
+def test_deposit_discrete_continuity_anisotropic_cells(orc, ndim, l):
+    """Continuity with cells of different size along each axis (the current
+    scales -Q dx_d/(Vc dt) and the divergence 1/dx_d must match)."""
+    rng = np.random.default_rng(40 + 10 * ndim + l)
+    n = (10, 9, 8)
+    g = orc.Grid(ndim, n[:ndim], l, 0.3, dx=(1.0, 0.7, 1.3))
+    for _ in range(15):
+        x0 = np.array([rng.uniform(0, n[d]) if d < ndim else 0.0 for d in range(3)])
+        dx = np.array([rng.uniform(-0.95, 0.95) if d < ndim else 0.0 for d in range(3)])
+        Q = rng.uniform(0.5, 2.0)
+        res, rho0 = _continuity_residual(orc, g, x0, x0 + dx, Q)
+        assert np.max(np.abs(res)) <= 1e-13 * Q / (g.s.dt * 0.7 * (1.3 if ndim == 3 else 1.0))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
 @pytest.mark.parametrize("l", [1, 2, 3, 4])
 def test_deposit_total_current(orc, ndim, l):
     """sum_cells J Vc = Q v: the current of one particle integrates to its
@@ -269,6 +285,27 @@ def test_vacuum_mode_dispersion_2d(orc, solver, a):
         g.field_update()
         assert np.max(np.abs(g.E[2] - np.cos(step * th) * E30)) <= 1e-12
     assert np.max(np.abs(g.E[:2])) <= 1e-12
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_vacuum_mode_dispersion_2d_anisotropic_cells(orc, solver):
+    """A vacuum mode on cells of 1 x 0.7 advances by the phase of the
+    dispersion relation with per-axis dx (Appendix C, A_i with per-axis
+    coefficients)."""
+    n = (16, 12)
+    dxs = (1.0, 0.7, 1.0)
+    a = 0.45
+    m1, m2 = 3, 2
+    k1, k2 = 2 * np.pi * m1 / (n[0] * dxs[0]), 2 * np.pi * m2 / (n[1] * dxs[1])
+    g = orc.Grid(2, n, 2, a * dxs[0], dx=dxs, solver=solver)
+    i = np.arange(g.ncell) % n[0]
+    j = np.arange(g.ncell) // n[0]
+    E30 = np.cos(2 * np.pi * m1 * i / n[0] + 2 * np.pi * m2 * j / n[1])
+    g.E[2] = E30
+    th = _mode_theta(solver, a, (k1, k2), dxs)
+    for step in range(1, 31):
+        g.field_update()
+        assert np.max(np.abs(g.E[2] - np.cos(step * th) * E30)) <= 1e-12
 
 
 @pytest.mark.parametrize("solver", [0, 1])
