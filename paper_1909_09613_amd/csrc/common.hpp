@@ -86,13 +86,13 @@ constexpr int kSpeciesShift = 30;
 struct DevState {
   int parity;                  // current particle store
   int sort_request;            // set when a tile's particles outgrew the staging margin
-  int sort_active;             // the sort sequence in flight works
+  int pad0;
   int tile_queue;              // next tile for the persistent particle kernel
   unsigned long long n_nonfinite;
   unsigned long long n_out_of_range;
   unsigned long long n_sorts;
   unsigned int groups_done;    // particle-kernel groups that found the queue empty
-  unsigned int pad2;
+  unsigned int arrange_done;   // sort arrange groups finished
 };
 
 template <class Real>

@@ -412,6 +412,8 @@ pic_status upload_static(pic_ctx* c) {
   if (e == hipSuccess) e = hipMemsetAsync(c->J, 0, c->lay.bytes[2], c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->P, 0, c->lay.bytes[0], c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->S + c->lay.s_state, 0, sizeof(DevState), c->stream);
+  // the sort keeps its counts and cursors zero between sorts
+  if (e == hipSuccess) e = hipMemsetAsync(c->S + c->lay.s_counts, 0, c->lay.s_seg - c->lay.s_counts, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return c->hip(e, "init upload");
 }

@@ -2,10 +2,10 @@
 // particles have outgrown the staging margin of the gather-push-deposit
 // kernel (a device-side request flag; all kernels exit at once otherwise).
 //
-// prep     one block: latch the request, clear counters
 // count    key = 2 * tile + species per particle; wave-aggregated counts
-// scan     one block: exclusive scan of the counts into segment offsets;
-//          reset every tile's box to its rectangle
+// scan     one block: exclusive scan of the counts into segment offsets
+//          (clearing the counts for the next sort); reset every tile's box to
+//          its rectangle
 // scatter  each particle to its segment of the other store
 // arrange  one block per segment: order the segment back into the current
 //          store by (rank within its cell, cell): first every cell's first
@@ -14,7 +14,11 @@
 //          nearby cells, one each, so that the gather reads and the current
 //          atomics of a wave touch distinct, nearly consecutive LDS
 //          addresses.  Ranks beyond `kcap` (dense cells) follow in cell order.
-// flip     clear the request, count the sort
+//          The last arrange block to finish clears the request and counts
+//          the sort.  Between sorts the counts and cursors are zero, so a
+//          sort needs no clearing pass, and every kernel reads the request
+//          flag itself (only the particle kernel sets it, and it does not
+//          run during a sort).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -55,25 +59,10 @@ __device__ int wave_add(int* ctr, int key, bool valid) {
 
 }  // namespace
 
-template <class Real>
-__global__ void sort_prep(SortArgs<Real> A) {
-  __shared__ int act;
-  if (threadIdx.x == 0) {
-    act = A.st->sort_request != 0;
-    A.st->sort_active = act;
-  }
-  __syncthreads();
-  if (!act) return;
-  for (int i = threadIdx.x; i < A.nkeys; i += blockDim.x) {
-    A.counts[i] = 0;
-    A.cursor[i] = 0;
-  }
-}
-
 template <class P, int DIM>
 __global__ void sort_count(SortArgs<typename P::Real> A) {
   using Real = typename P::Real;
-  if (!A.st->sort_active) return;
+  if (!A.st->sort_request) return;
   const PBuf<Real> B = A.buf[A.st->parity];
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long start = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -112,7 +101,7 @@ __global__ void sort_count(SortArgs<typename P::Real> A) {
 
 template <class Real>
 __global__ void sort_scan(SortArgs<Real> A) {
-  if (!A.st->sort_active) return;
+  if (!A.st->sort_request) return;
   __shared__ long long part[1024];
   const int tid = threadIdx.x, nth = blockDim.x;
   const int chunk = (A.nkeys + nth - 1) / nth;
@@ -132,6 +121,7 @@ __global__ void sort_scan(SortArgs<Real> A) {
   for (int i = lo; i < hi; ++i) {
     A.seg[i] = (int)base;
     base += A.counts[i];
+    A.counts[i] = 0;
   }
   if (tid == nth - 1) A.seg[A.nkeys] = (int)part[nth - 1];
   // every tile's particles now lie in its rectangle; its current bounds are
@@ -155,7 +145,7 @@ __global__ void sort_scan(SortArgs<Real> A) {
 template <class P, int DIM>
 __global__ void sort_scatter(SortArgs<typename P::Real> A) {
   using Real = typename P::Real;
-  if (!A.st->sort_active) return;
+  if (!A.st->sort_request) return;
   const int par = A.st->parity;
   const PBuf<Real> S = A.buf[par];
   const PBuf<Real> D = A.buf[par ^ 1];
@@ -212,7 +202,7 @@ __device__ __forceinline__ int cell_in_tile(const PBuf<typename P::Real>& S, lon
 template <class P, int DIM>
 __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename P::Real> A) {
   using Real = typename P::Real;
-  if (!A.st->sort_active) return;
+  if (!A.st->sort_request) return;
   extern __shared__ __align__(16) int sm[];
   __shared__ int cmax_s;
   const int TC = A.tc, KC = A.kcap;
@@ -226,6 +216,8 @@ __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename 
   const PBuf<Real> S = A.buf[par ^ 1];
   const PBuf<Real> D = A.buf[par];
   const unsigned long long below = (1ull << lane) - 1ull;
+  // the scatter is done with the cursors: clear them for the next sort
+  for (int i = blockIdx.x * kArrangeBlock + tid; i < A.nkeys; i += gridDim.x * kArrangeBlock) A.cursor[i] = 0;
   for (int key = blockIdx.x; key < A.nkeys; key += gridDim.x) {
     const int s0 = A.seg[key];
     const int n = A.seg[key + 1] - s0;
@@ -319,22 +311,22 @@ __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename 
     }
     __syncthreads();
   }
-}
-
-template <class Real>
-__global__ void sort_flip(SortArgs<Real> A) {
-  if (!A.st->sort_active) return;
-  A.st->sort_request = 0;
-  A.st->sort_active = 0;
-  A.st->n_sorts += 1;
+  // the last group to finish ends the sort (every group has started and
+  // read the request by then)
+  if (tid == 0 && atomicAdd(&A.st->arrange_done, 1u) == gridDim.x - 1) {
+    A.st->arrange_done = 0;
+    A.st->n_sorts += 1;
+    A.st->sort_request = 0;
+  }
 }
 
 template <class P>
 hipError_t launch_sort(const SortArgs<typename P::Real>& a, int ndim, hipStream_t s) {
   using Real = typename P::Real;
   const long long blocks = (a.np_total + 255) / 256;
-  const int grid = (int)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
-  hipLaunchKernelGGL(sort_prep<Real>, dim3(1), dim3(1024), 0, s, a);
+  // grid-stride kernels: enough groups to fill the chip when a sort runs,
+  // few enough that the launches between sorts (all exit at once) are cheap
+  const int grid = (int)(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024);
   if (ndim == 2)
     hipLaunchKernelGGL((sort_count<P, 2>), dim3(grid), dim3(256), 0, s, a);
   else
@@ -344,12 +336,11 @@ hipError_t launch_sort(const SortArgs<typename P::Real>& a, int ndim, hipStream_
     hipLaunchKernelGGL((sort_scatter<P, 2>), dim3(grid), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((sort_scatter<P, 3>), dim3(grid), dim3(256), 0, s, a);
-  const int agrid = a.nkeys < 2048 ? a.nkeys : 2048;
+  const int agrid = a.nkeys < 512 ? a.nkeys : 512;
   if (ndim == 2)
     hipLaunchKernelGGL((sort_arrange<P, 2>), dim3(agrid), dim3(kArrangeBlock), arrange_lds(a.tc, a.kcap), s, a);
   else
     hipLaunchKernelGGL((sort_arrange<P, 3>), dim3(agrid), dim3(kArrangeBlock), arrange_lds(a.tc, a.kcap), s, a);
-  hipLaunchKernelGGL(sort_flip<Real>, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }
 
