@@ -202,6 +202,14 @@ def main():
     ms_graph = float(np.median(graph_ms))
 
     d = sim.diagnostics(0)
+    # one diagnostics call (energies, momentum, Gauss residual) after steps,
+    # host clock around the whole call, median of three
+    diag_ms = []
+    for _ in range(3):
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.diagnostics(0)
+        diag_ms.append((time.perf_counter() - t0) * 1e3)
     sim.close()
 
     # the step rate: pic_step replays of the captured step graph (the
@@ -255,6 +263,7 @@ def main():
             "rest_of_step_ms": ms_total / args.steps - gpd_ms,
             "first_step_with_full_sort_ms": ms_sort_step,
             "sorts_in_timed_region": d.n_sorts - d0.n_sorts,
+            "diagnostics_call_ms": float(np.median(diag_ms)),
         },
         "cpu_baseline": cpu,
         "check": {"n_nonfinite": d.n_nonfinite, "n_out_of_range": d.n_out_of_range, "n_sorts": d.n_sorts,

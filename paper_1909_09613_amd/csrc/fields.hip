@@ -160,6 +160,9 @@ template hipError_t launch_fill<int>(int*, long long, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // Diagnostics (FP64).  acc: [0..2] sum E_d^2, [3..5] sum B_d^2, [6..7] sum
 // M (gamma-1) c^2 per species, [8..10] sum M u c, [11] max |D.E - rho| (bits).
+// The sums are taken per block into part[block][16] and then added block by
+// block in a fixed order, so that repeated diagnostics of one state agree
+// to the last bit.
 // ---------------------------------------------------------------------------
 
 namespace {
@@ -179,7 +182,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }  // namespace
 
 template <class Real>
-__global__ void diag_fields_kernel(DiagArgs<Real> A, long long cells) {
+__global__ void __launch_bounds__(256) diag_fields_kernel(DiagArgs<Real> A, long long cells) {
   __shared__ double sh[16];
   const RunDev<Real>& R = A.runs[A.run];
   const Real* F = A.F + R.cell0;
@@ -195,12 +198,12 @@ __global__ void diag_fields_kernel(DiagArgs<Real> A, long long cells) {
   }
   for (int c = 0; c < 6; ++c) {
     const double t = block_sum(s[c], sh);
-    if (threadIdx.x == 0) atomicAdd(&A.acc[c], t);
+    if (threadIdx.x == 0) A.part[16 * blockIdx.x + c] = t;
   }
 }
 
 template <class P, int DIM>
-__global__ void diag_particles_kernel(DiagArgs<typename P::Real> A, long long p0, long long np) {
+__global__ void __launch_bounds__(256) diag_particles_kernel(DiagArgs<typename P::Real> A, long long p0, long long np) {
   using Real = typename P::Real;
   __shared__ double sh[16];
   const RunDev<Real>& R = A.runs[A.run];
@@ -221,10 +224,24 @@ __global__ void diag_particles_kernel(DiagArgs<typename P::Real> A, long long p0
   }
   for (int c = 0; c < 5; ++c) {
     const double t = block_sum(s[c], sh);
-    if (threadIdx.x == 0) atomicAdd(&A.acc[6 + c], t);
+    if (threadIdx.x == 0) A.part[16 * blockIdx.x + 6 + c] = t;
   }
 }
 
+// acc[c] = sum over blocks of part[block][c]: the field sums over nbf
+// blocks, the particle sums over nbp blocks; one wave per accumulator, each
+// lane a fixed stride of blocks, then a fixed butterfly.
+__global__ void __launch_bounds__(704) diag_final_kernel(double* acc, const double* part, int nbf, int nbp) {
+  const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nb = (c < 6) ? nbf : nbp;
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += part[16 * b + c];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) acc[c] = s;
+}
+
+// Global-atomic variant for particles that are not in tile order (before the
+// first step after particles were set); the tiled kernel is in gpd.hip.
 // rho(m) += (Q/Vc) prod_d W_l(x_d - m_d) on integer nodes (Eq. shape-real).
 template <class P, int L, int DIM>
 __global__ void diag_rho_kernel(DiagArgs<typename P::Real> A, long long p0, long long np) {
@@ -279,12 +296,15 @@ __global__ void diag_gauss_kernel(DiagArgs<Real> A, long long cells) {
   const RunDev<Real>& R = A.runs[A.run];
   const Real* F = A.F + R.cell0;
   const long long NT = A.ncell_total;
-  const long long stride = (long long)gridDim.x * blockDim.x;
+  // a run has fewer than 2^30 cells (one particle per species per cell at
+  // least, fewer than 2^31 particles)
+  const int stride = gridDim.x * blockDim.x;
+  const int nxy = R.n[0] * R.n[1];
   double mx = 0.0;
-  for (long long ci = (long long)blockIdx.x * blockDim.x + threadIdx.x; ci < cells; ci += stride) {
-    const int i = (int)(ci % R.n[0]);
-    const int j = (int)((ci / R.n[0]) % R.n[1]);
-    const int k = (int)(ci / ((long long)R.n[0] * R.n[1]));
+  for (int ci = blockIdx.x * blockDim.x + threadIdx.x; ci < (int)cells; ci += stride) {
+    const int i = ci % R.n[0];
+    const int j = (ci / R.n[0]) % R.n[1];
+    const int k = ci / nxy;
     double div = 0.0;
     for (int d = 0; d < DIM; ++d) {
       const int pi = (d == 0) ? wrapi(i - 1, R.n[0]) : i;
@@ -305,36 +325,51 @@ __global__ void diag_gauss_kernel(DiagArgs<Real> A, long long cells) {
 
 template <class P>
 hipError_t launch_diag(const DiagArgs<typename P::Real>& a, int ndim, int order, long long cells, long long p0,
-                       long long np, hipStream_t s) {
+                       long long np, bool rho_done, hipStream_t s) {
   using Real = typename P::Real;
   auto grid_for = [](long long n) {
     long long b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > kDiagBlocks ? kDiagBlocks : b));
+  };
+  auto rho_grid = [](long long n) {
+    long long b = (n + 255) / 256;
     return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
   };
-  hipLaunchKernelGGL(diag_fields_kernel<Real>, dim3(grid_for(cells)), dim3(256), 0, s, a, cells);
-  if (ndim == 2) {
-    hipLaunchKernelGGL((diag_particles_kernel<P, 2>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np);
-    switch (order) {
-      case 1: hipLaunchKernelGGL((diag_rho_kernel<P, 1, 2>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
-      case 2: hipLaunchKernelGGL((diag_rho_kernel<P, 2, 2>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
-      case 3: hipLaunchKernelGGL((diag_rho_kernel<P, 3, 2>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
-      case 4: hipLaunchKernelGGL((diag_rho_kernel<P, 4, 2>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
+  const unsigned nbf = grid_for(cells), nbp = grid_for(np);
+  hipLaunchKernelGGL(diag_fields_kernel<Real>, dim3(nbf), dim3(256), 0, s, a, cells);
+  if (ndim == 2)
+    hipLaunchKernelGGL((diag_particles_kernel<P, 2>), dim3(nbp), dim3(256), 0, s, a, p0, np);
+  else
+    hipLaunchKernelGGL((diag_particles_kernel<P, 3>), dim3(nbp), dim3(256), 0, s, a, p0, np);
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(11 * 64), 0, s, a.acc, a.part, (int)nbf, (int)nbp);
+  if (!rho_done) {
+    const dim3 rg(rho_grid(np)), rb(256);
+    if (ndim == 2) {
+      switch (order) {
+        case 1: hipLaunchKernelGGL((diag_rho_kernel<P, 1, 2>), rg, rb, 0, s, a, p0, np); break;
+        case 2: hipLaunchKernelGGL((diag_rho_kernel<P, 2, 2>), rg, rb, 0, s, a, p0, np); break;
+        case 3: hipLaunchKernelGGL((diag_rho_kernel<P, 3, 2>), rg, rb, 0, s, a, p0, np); break;
+        case 4: hipLaunchKernelGGL((diag_rho_kernel<P, 4, 2>), rg, rb, 0, s, a, p0, np); break;
+      }
+    } else {
+      switch (order) {
+        case 1: hipLaunchKernelGGL((diag_rho_kernel<P, 1, 3>), rg, rb, 0, s, a, p0, np); break;
+        case 2: hipLaunchKernelGGL((diag_rho_kernel<P, 2, 3>), rg, rb, 0, s, a, p0, np); break;
+        case 3: hipLaunchKernelGGL((diag_rho_kernel<P, 3, 3>), rg, rb, 0, s, a, p0, np); break;
+        case 4: hipLaunchKernelGGL((diag_rho_kernel<P, 4, 3>), rg, rb, 0, s, a, p0, np); break;
+      }
     }
-    hipLaunchKernelGGL((diag_gauss_kernel<Real, 2>), dim3(grid_for(cells)), dim3(256), 0, s, a, cells);
-  } else {
-    hipLaunchKernelGGL((diag_particles_kernel<P, 3>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np);
-    switch (order) {
-      case 1: hipLaunchKernelGGL((diag_rho_kernel<P, 1, 3>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
-      case 2: hipLaunchKernelGGL((diag_rho_kernel<P, 2, 3>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
-      case 3: hipLaunchKernelGGL((diag_rho_kernel<P, 3, 3>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
-      case 4: hipLaunchKernelGGL((diag_rho_kernel<P, 4, 3>), dim3(grid_for(np)), dim3(256), 0, s, a, p0, np); break;
-    }
-    hipLaunchKernelGGL((diag_gauss_kernel<Real, 3>), dim3(grid_for(cells)), dim3(256), 0, s, a, cells);
   }
+  if (ndim == 2)
+    hipLaunchKernelGGL((diag_gauss_kernel<Real, 2>), dim3(grid_for(cells)), dim3(256), 0, s, a, cells);
+  else
+    hipLaunchKernelGGL((diag_gauss_kernel<Real, 3>), dim3(grid_for(cells)), dim3(256), 0, s, a, cells);
   return hipGetLastError();
 }
 
-template hipError_t launch_diag<F32>(const DiagArgs<float>&, int, int, long long, long long, long long, hipStream_t);
-template hipError_t launch_diag<F64>(const DiagArgs<double>&, int, int, long long, long long, long long, hipStream_t);
+template hipError_t launch_diag<F32>(const DiagArgs<float>&, int, int, long long, long long, long long, bool,
+                                     hipStream_t);
+template hipError_t launch_diag<F64>(const DiagArgs<double>&, int, int, long long, long long, long long, bool,
+                                     hipStream_t);
 
 }  // namespace wtpic

@@ -828,6 +828,158 @@ static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hip
   return hipGetLastError();
 }
 
+// Charge density of one run for the diagnostics, tile by tile (Eq.
+// shape-real: rho(m) += (Q/Vc) prod_d W_l(x_d - m_d) on integer nodes).
+// Each workgroup takes tiles of the run; it adds its tile's particles into an
+// FP64 LDS window over the tile's box plus the form-factor reach and then
+// adds the window to the global array.  The particles must sit in their
+// tiles' segments with boxes from the last step (as after any step); a
+// particle outside the window (not expected) is added to global memory
+// directly.
+template <class P, int L, int DIM>
+__global__ void __launch_bounds__(256) rho_tiles_kernel(GpdArgs<typename P::Real> A, int run, double* rho) {
+  using Real = typename P::Real;
+  extern __shared__ __align__(16) unsigned char lds_dyn[];
+  double* W = reinterpret_cast<double*>(lds_dyn);
+  const RunDev<Real>& R = A.runs[run];
+  const int ntiles = R.ntile[0] * R.ntile[1] * R.ntile[2];
+  const int jwx = A.jw[0], jwy = A.jw[1];
+  const int jcap = jwx * jwy * (DIM == 3 ? A.jw[2] : 1);
+  const PBuf<Real> B = A.buf[A.st->parity];
+  const int tid = threadIdx.x;
+  const double qv[2] = {R.Q[0] / R.Vc, R.Q[1] / R.Vc};
+  for (int lt = blockIdx.x; lt < ntiles; lt += gridDim.x) {
+    const int g = R.tile0 + lt;
+    int org[3];
+    org[0] = (lt % R.ntile[0]) * A.tile[0];
+    org[1] = ((lt / R.ntile[0]) % R.ntile[1]) * A.tile[1];
+    org[2] = (DIM == 3) ? (lt / (R.ntile[0] * R.ntile[1])) * A.tile[2] : 0;
+    int jo[3] = {0, 0, 0}, jsz[3] = {1, 1, 1}, co[3] = {0, 0, 0}, lo_[3] = {0, 0, 0}, rlo[3] = {0, 0, 0},
+        rhi[3] = {0, 0, 0};
+    bool fits = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int blo = A.bbox[g * 6 + 2 * d], bhi = A.bbox[g * 6 + 2 * d + 1];
+      jo[d] = blo + R.dlo[d];
+      jsz[d] = bhi + R.dhi[d] - jo[d] + 1;
+      fits = fits && jsz[d] >= 1 && jsz[d] <= A.jw[d];
+      const int slack = max(0, R.n[d] - 1 - (bhi - blo));
+      lo_[d] = blo - (slack >> 1);
+      co[d] = org[d] + lo_[d];
+      // a particle's nodes are rel + (base - cell) + first .. + L with
+      // base - cell in {-1, 0}
+      rlo[d] = jo[d] + 1 - R.Wi[d].first;
+      rhi[d] = jo[d] + jsz[d] - 1 - L - R.Wi[d].first;
+    }
+    if (!fits) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) rlo[d] = INT_MAX;  // every particle takes the global path
+    }
+    for (int i = tid; i < jcap; i += blockDim.x) W[i] = 0.0;
+    __syncthreads();
+    const int sA = A.seg[2 * g], sB = A.seg[2 * g + 1], sC = A.seg[2 * g + 2];
+    for (int p = sA + tid; p < sC; p += blockDim.x) {
+      const int sp = (p >= sB) ? 1 : 0;
+      int c[3] = {0, 0, 0};
+      Real f[3] = {Real(0), Real(0), Real(0)};
+      if (P::kAbs) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const Real x = B.pos[d][p];
+          const Real fl = floor(x);
+          c[d] = (int)fl;
+          f[d] = x - fl;
+        }
+      } else {
+        unpack_cell<DIM>(B.cell[p], c[0], c[1], c[2]);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) f[d] = B.pos[d][p];
+      }
+      Real w[3][L + 1];
+      int m[3] = {0, 0, 0}, mg[3] = {0, 0, 0};
+      bool inwin = true;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        int b;
+        Real gg;
+        tab_split(R.Wi[d], c[d], f[d], b, gg);
+        tab_eval<L, L + 1, false>(R.Wi[d], gg, w[d]);
+        const int rel = wrap_near(c[d] - co[d], R.n[d]) + lo_[d];
+        inwin = inwin && rel >= rlo[d] && rel <= rhi[d];
+        m[d] = rel + (b - c[d]) + R.Wi[d].first - jo[d];  // window index of the first node
+        mg[d] = b + R.Wi[d].first;                        // its lattice index
+      }
+      const double q = qv[sp];
+      const int nz = (DIM == 3) ? L + 1 : 1;
+      for (int kz = 0; kz < nz; ++kz)
+#pragma unroll
+        for (int ky = 0; ky <= L; ++ky) {
+          double wyz = q * (double)w[1][ky];
+          if (DIM == 3) wyz *= (double)w[2][kz];
+#pragma unroll
+          for (int kx = 0; kx <= L; ++kx) {
+            const double v = wyz * (double)w[0][kx];
+            if (inwin) {
+              atomicAdd(W + (m[0] + kx) + jwx * ((m[1] + ky) + jwy * (m[2] + kz)), v);
+            } else {
+              const int gx = wrapi(mg[0] + kx, R.n[0]), gy = wrapi(mg[1] + ky, R.n[1]);
+              const int gz = (DIM == 3) ? wrapi(mg[2] + kz, R.n[2]) : 0;
+              unsafeAtomicAdd(rho + gx + (long long)R.n[0] * (gy + (long long)R.n[1] * gz), v);
+            }
+          }
+        }
+    }
+    __syncthreads();
+    const int njs = fits ? jsz[0] * jsz[1] * jsz[2] : 0;
+    for (int i = tid; i < njs; i += blockDim.x) {
+      const int w0 = i % jsz[0];
+      const int q = i / jsz[0];
+      const int w1 = q % jsz[1];
+      const int w2 = q / jsz[1];
+      const double v = W[w0 + jwx * (w1 + jwy * w2)];
+      if (v == 0.0) continue;
+      const int gx = wrapi(org[0] + jo[0] + w0, R.n[0]);
+      const int gy = wrapi(org[1] + jo[1] + w1, R.n[1]);
+      const int gz = (DIM == 3) ? wrapi(org[2] + jo[2] + w2, R.n[2]) : 0;
+      unsafeAtomicAdd(rho + gx + (long long)R.n[0] * (gy + (long long)R.n[1] * gz), v);
+    }
+    __syncthreads();
+  }
+}
+
+template <class P, int L, int DIM>
+static hipError_t launch_rho_one(const GpdArgs<typename P::Real>& a, int run, int ntiles, double* rho, size_t lds,
+                                 hipStream_t s) {
+  const int grid = ntiles < 2048 ? ntiles : 2048;
+  hipLaunchKernelGGL((rho_tiles_kernel<P, L, DIM>), dim3(grid), dim3(256), lds, s, a, run, rho);
+  return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_rho_tiles(const GpdArgs<typename P::Real>& a, int run, int ntiles, double* rho, int order,
+                            int ndim, size_t lds, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (ndim == 2) {
+    switch (order) {
+      case 1: return launch_rho_one<P, 1, 2>(a, run, ntiles, rho, lds, s);
+      case 2: return launch_rho_one<P, 2, 2>(a, run, ntiles, rho, lds, s);
+      case 3: return launch_rho_one<P, 3, 2>(a, run, ntiles, rho, lds, s);
+      case 4: return launch_rho_one<P, 4, 2>(a, run, ntiles, rho, lds, s);
+    }
+  } else {
+    switch (order) {
+      case 1: return launch_rho_one<P, 1, 3>(a, run, ntiles, rho, lds, s);
+      case 2: return launch_rho_one<P, 2, 3>(a, run, ntiles, rho, lds, s);
+      case 3: return launch_rho_one<P, 3, 3>(a, run, ntiles, rho, lds, s);
+      case 4: return launch_rho_one<P, 4, 3>(a, run, ntiles, rho, lds, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_rho_tiles<F32>(const GpdArgs<float>&, int, int, double*, int, int, size_t, hipStream_t);
+template hipError_t launch_rho_tiles<F64>(const GpdArgs<double>&, int, int, double*, int, int, size_t, hipStream_t);
+
 template <class P>
 hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, size_t lds, hipStream_t s) {
   if (ndim == 2) {

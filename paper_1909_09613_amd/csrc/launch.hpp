@@ -59,11 +59,21 @@ struct DiagArgs {
   const Real* F;
   long long ncell_total;
   double* acc;             // 16 accumulators (see diag kernels)
+  double* part;            // kDiagBlocks x 16 per-block partial sums
   double* rho;             // ncell of the run
 };
 
+// Blocks of the diagnostics sums (each leaves 16 partial sums).
+constexpr int kDiagBlocks = 2048;
+
 template <class P>
 hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, size_t lds, hipStream_t s);
+
+// Charge density of one run from the tile segments (diagnostics); lds bytes
+// must hold 8 * (current window nodes).
+template <class P>
+hipError_t launch_rho_tiles(const GpdArgs<typename P::Real>& a, int run, int ntiles, double* rho, int order,
+                            int ndim, size_t lds, hipStream_t s);
 
 template <class P>
 hipError_t launch_sort(const SortArgs<typename P::Real>& a, int ndim, hipStream_t s);
@@ -77,6 +87,6 @@ hipError_t launch_fill(Real* p, long long n, Real v, hipStream_t s);
 
 template <class P>
 hipError_t launch_diag(const DiagArgs<typename P::Real>& a, int ndim, int order, long long cells,
-                       long long p0, long long np, hipStream_t s);
+                       long long p0, long long np, bool rho_done, hipStream_t s);
 
 }  // namespace wtpic

@@ -48,7 +48,7 @@ struct Layout {
   // fields / current: component-major
   // scratch
   size_t s_state, s_runs, s_tile_run, s_counts, s_cursor, s_seg, s_bbox, s_jb, s_keys, s_blk_run, s_blk_first, s_acc,
-      s_rho;
+      s_part, s_rho;
   long long gmax;
   long long nblocks;
 };
@@ -176,6 +176,8 @@ Layout make_layout(const pic_run_desc* runs, int n_runs) {
   off += align_up(4 * nblocks);
   L.s_acc = off;
   off += align_up(8 * 16);
+  L.s_part = off;
+  off += align_up(8 * 16 * (size_t)kDiagBlocks);
   L.s_rho = off;
   off += align_up(8 * maxc);
   L.bytes[3] = off;
@@ -714,10 +716,19 @@ pic_status diag_t(pic_ctx* c, int run, pic_diag* out) {
   a.F = reinterpret_cast<const Real*>(c->F);
   a.ncell_total = c->ncell_total;
   a.acc = reinterpret_cast<double*>(c->S + c->lay.s_acc);
+  a.part = reinterpret_cast<double*>(c->S + c->lay.s_part);
   a.rho = reinterpret_cast<double*>(c->S + c->lay.s_rho);
+  // after a step the particles sit in their tiles' segments and the charge
+  // density is accumulated tile by tile; right after particles were set it
+  // takes the global-atomic kernel
+  const bool tiled = c->sorted_once && !c->force_sort;
   hipError_t e = launch_fill<double>(a.acc, 16, 0.0, c->stream);
   if (e == hipSuccess) e = launch_fill<double>(a.rho, H.ncell, 0.0, c->stream);
-  if (e == hipSuccess) e = launch_diag<P>(a, c->ndim, c->order, H.ncell, H.p0, 2 * H.nps, c->stream);
+  if (e == hipSuccess && tiled) {
+    const size_t jcap = (size_t)c->jw[0] * c->jw[1] * c->jw[2];
+    e = launch_rho_tiles<P>(gpd_args<Real>(c), run, H.ntiles, a.rho, c->order, c->ndim, 8 * jcap, c->stream);
+  }
+  if (e == hipSuccess) e = launch_diag<P>(a, c->ndim, c->order, H.ncell, H.p0, 2 * H.nps, tiled, c->stream);
   double acc[16];
   DevState ds{};
   if (e == hipSuccess) e = host_copy(c, acc, a.acc, sizeof acc, hipMemcpyDeviceToHost);

@@ -348,6 +348,49 @@ def test_diagnostics_match_oracle(orc):
     assert abs(d.gauss_resid_max - r) <= 1e-10 * max(r, 1e-300) + 1e-14
 
 
+@pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32], ids=["fp64", "fp32"])
+def test_diagnostics_tiled_rho_and_repeatable(orc, precision):
+    """After steps the charge density of the Gauss residual is accumulated
+    tile by tile; setting the particles again (which leaves them out of tile
+    order until the next sort) sends the same state through the global-atomic
+    kernel.  Both give the residual the oracle computes from the GPU's own
+    particles and E, and the field and particle sums of two calls agree to
+    the last bit."""
+    spec = RunSpec(2, (64, 40), 3, 0.45, 50.0, 0.01, 4, 72, colocated=False, skin_depth_cells=4.0)
+    sp = inputs.make_species(spec)
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, sp)
+        sim.step(6)
+        d1 = sim.diagnostics(0)
+        d2 = sim.diagnostics(0)
+        got = [sim.particles(0, s) for s in range(2)]
+        E, _, _ = sim.fields(0)
+        again = H.copy_species(sp)
+        for s in range(2):
+            again[s]["x"], again[s]["u"] = got[s][0].copy(), got[s][1].copy()
+        sim.set_species(0, again)
+        d3 = sim.diagnostics(0)
+    finally:
+        sim.close()
+    for a, b in ((d1, d2),):
+        assert list(a.UE) == list(b.UE) and list(a.UB) == list(b.UB)
+        assert list(a.Ekin) == list(b.Ekin) and list(a.momentum) == list(b.momentum)
+    g = H.oracle_grid(orc, spec)
+    g.E[:] = E
+    ref = H.copy_species(sp)
+    for s in range(2):
+        ref[s]["x"], ref[s]["u"] = got[s][0].copy(), got[s][1].copy()
+    r = np.max(np.abs(g.gauss_residual(ref)))
+    rho_s = spec.ppc_s * abs(sp[0]["Q"]) / spec.Vc
+    tol = (1e-12 if precision == wt.PIC_FP64 else 1e-6) * rho_s
+    print("gauss tiled %.3e global %.3e oracle %.3e rho_s %.3e" % (d1.gauss_resid_max, d3.gauss_resid_max, r, rho_s),
+          flush=True)
+    assert abs(d1.gauss_resid_max - r) <= tol
+    assert abs(d3.gauss_resid_max - r) <= tol
+    assert abs(d1.gauss_resid_max - d3.gauss_resid_max) <= tol
+
+
 def test_counters_report_nonfinite(orc):
     """A non-finite momentum is counted, left in place, and surfaced by
     pic_diagnostics as PIC_ERR_NUMERIC; the other particles are unaffected."""
