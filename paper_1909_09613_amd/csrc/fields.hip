@@ -9,13 +9,19 @@ namespace wtpic {
 
 namespace {
 
+// Index on a periodic axis for -n <= m < 2n (stencil neighbours of a cell).
+__device__ __forceinline__ int wrap1(int m, int n) {
+  return m < 0 ? m + n : (m >= n ? m - n : m);
+}
+
+// A component of one run; a run has fewer than 2^30 cells (at least one
+// particle per species per cell, fewer than 2^31 particles), so indices fit
+// in 32 bits.
 template <class Real>
 struct Grid3 {
   const Real* f;
   int n0, n1, n2;
-  __device__ Real at(int i, int j, int k) const {
-    return f[wrapi(i, n0) + (long long)n0 * (wrapi(j, n1) + (long long)n1 * wrapi(k, n2))];
-  }
+  __device__ Real at(int i, int j, int k) const { return f[wrap1(i, n0) + n0 * (wrap1(j, n1) + n1 * wrap1(k, n2))]; }
 };
 
 // Forward staggered difference along d of a component at node (i, j, k).
@@ -61,12 +67,13 @@ template <class Real, int DIM, bool M4>
 __global__ void __launch_bounds__(256) faraday_kernel(FieldArgs<Real> A) {
   const int b = blockIdx.x;
   const RunDev<Real>& R = A.runs[A.blk_run[b]];
-  const long long nc = (long long)R.n[0] * R.n[1] * R.n[2];
-  const long long ci = A.blk_first[b] + threadIdx.x;
-  if (ci >= nc) return;
-  const int i = (int)(ci % R.n[0]);
-  const int j = (int)((ci / R.n[0]) % R.n[1]);
-  const int k = (int)(ci / ((long long)R.n[0] * R.n[1]));
+  const int nxy = R.n[0] * R.n[1];
+  const int ci = A.blk_first[b] + threadIdx.x;
+  if (ci >= nxy * R.n[2]) return;
+  const int q = ci / R.n[0];
+  const int i = ci - q * R.n[0];
+  const int j = (DIM == 2) ? q : q % R.n[1];
+  const int k = (DIM == 2) ? 0 : q / R.n[1];
   const long long NT = A.ncell_total;
   Real* F = A.F + R.cell0;
   const Grid3<Real> E1{F, R.n[0], R.n[1], R.n[2]}, E2{F + NT, R.n[0], R.n[1], R.n[2]},
@@ -84,12 +91,13 @@ template <class Real, int DIM>
 __global__ void __launch_bounds__(256) ampere_kernel(FieldArgs<Real> A) {
   const int b = blockIdx.x;
   const RunDev<Real>& R = A.runs[A.blk_run[b]];
-  const long long nc = (long long)R.n[0] * R.n[1] * R.n[2];
-  const long long ci = A.blk_first[b] + threadIdx.x;
-  if (ci >= nc) return;
-  const int i = (int)(ci % R.n[0]);
-  const int j = (int)((ci / R.n[0]) % R.n[1]);
-  const int k = (int)(ci / ((long long)R.n[0] * R.n[1]));
+  const int nxy = R.n[0] * R.n[1];
+  const int ci = A.blk_first[b] + threadIdx.x;
+  if (ci >= nxy * R.n[2]) return;
+  const int q = ci / R.n[0];
+  const int i = ci - q * R.n[0];
+  const int j = (DIM == 2) ? q : q % R.n[1];
+  const int k = (DIM == 2) ? 0 : q / R.n[1];
   const long long NT = A.ncell_total;
   Real* F = A.F + R.cell0;
   double* J = A.J + R.cell0;
