@@ -64,6 +64,13 @@ void orc_wrap(const orc_grid *g, double *x);
 /* Whole-species and whole-grid steps. */
 void orc_zero_J(orc_grid *g);
 void orc_push_species(orc_grid *g, long np, double *x, double *u, double qm, double Q);
+
+/* Partially skipped calculation (Sec. 3): A(t) membership of a canonical
+ * position for the box lo..hi (cell units, periodic), and the species step in
+ * which particles outside A(t) only drift. */
+int orc_perturbed(const orc_grid *g, const double *x, const double *lo, const double *hi, double t);
+void orc_push_species_skip(orc_grid *g, long np, double *x, double *u, double qm, double Q, const double *lo,
+                           const double *hi, double t);
 void orc_faraday_half(orc_grid *g);
 void orc_ampere(orc_grid *g);
 void orc_field_update(orc_grid *g);

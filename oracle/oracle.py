@@ -66,6 +66,8 @@ def _declare(L):
         "orc_wrap": (None, [g, _dp]),
         "orc_zero_J": (None, [g]),
         "orc_push_species": (None, [g, l_, _dp, _dp, d, d]),
+        "orc_perturbed": (i, [g, _dp, _dp, _dp, d]),
+        "orc_push_species_skip": (None, [g, l_, _dp, _dp, d, d, _dp, _dp, d]),
         "orc_faraday_half": (None, [g]), "orc_ampere": (None, [g]),
         "orc_field_update": (None, [g]),
         "orc_rho": (None, [g, l_, _dp, d, _dp]),
@@ -171,10 +173,29 @@ class Grid:
     def zero_J(self):
         lib().orc_zero_J(self.ref)
 
-    def push_species(self, x, u, qm, Q):
-        """Gather + Boris + move + deposit (+ wrap) for one species, in place."""
+    def push_species(self, x, u, qm, Q, skip=None):
+        """Gather + Boris + move + deposit (+ wrap) for one species, in place.
+
+        skip = (lo, hi, t): particles outside the region perturbed at time t
+        around the box lo..hi only drift (partially skipped calculation)."""
         assert x.shape == u.shape and x.shape[1] == 3
-        lib().orc_push_species(self.ref, len(x), _ptr(x), _ptr(u), float(qm), float(Q))
+        if skip is None:
+            lib().orc_push_species(self.ref, len(x), _ptr(x), _ptr(u), float(qm), float(Q))
+        else:
+            lo, hi, t = skip
+            lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(3)
+            hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(3)
+            lib().orc_push_species_skip(self.ref, len(x), _ptr(x), _ptr(u), float(qm), float(Q),
+                                        _ptr(lo), _ptr(hi), float(t))
+
+    def perturbed(self, x, lo, hi, t):
+        """1 where the canonical positions x (np, 3) lie in the region
+        perturbed at time t around the box lo..hi."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(3)
+        hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(3)
+        return np.array([lib().orc_perturbed(self.ref, _ptr(np.ascontiguousarray(x[p])), _ptr(lo), _ptr(hi),
+                                             float(t)) for p in range(len(x))], dtype=np.int32)
 
     def field_update(self):
         lib().orc_field_update(self.ref)
@@ -185,14 +206,15 @@ class Grid:
     def ampere(self):
         lib().orc_ampere(self.ref)
 
-    def step(self, species):
+    def step(self, species, skip=None):
         """One PIC step: zero J, push every species, update the fields.
 
-        species: list of dicts with keys x, u (arrays (np, 3)), qm, Q.
+        species: list of dicts with keys x, u (arrays (np, 3)), qm, Q;
+        skip: as for push_species.
         """
         self.zero_J()
         for s in species:
-            self.push_species(s["x"], s["u"], s["qm"], s["Q"])
+            self.push_species(s["x"], s["u"], s["qm"], s["Q"], skip)
         self.field_update()
 
     # -- diagnostics --------------------------------------------------------
