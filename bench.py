@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--tile", default=None, help="tile shape, e.g. 32x16")
     ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5], help="workload")
+    ap.add_argument("--skip-strip", type=float, default=0.0,
+                    help="partially skipped calculation: initially perturbed strip of this width (cells, "
+                         "across x1 at the grid centre); 0 = off")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -142,6 +145,11 @@ def main():
         wt.pic_set_tiling(sim.ctx, tuple(t[:3]), 0, 0)
     for r, sr in enumerate(specs):
         sim.set_species(r, inputs.make_species(sr))
+    if args.skip_strip > 0:
+        for r, sr in enumerate(specs):
+            mid = 0.5 * sr.n[0]
+            sim.set_skip_region(r, (mid - 0.5 * args.skip_strip, 0.0, 0.0),
+                                (mid + 0.5 * args.skip_strip, float(sr.n[1]), float(sr.n3[2])), 0.0)
     np_total = sum(2 * sr.ncell * sr.ppc_s for sr in specs)
     ncell_total = sum(sr.ncell for sr in specs)
     print("setup %.1f s, %d particles" % (time.perf_counter() - t_setup, np_total), file=sys.stderr, flush=True)
@@ -202,6 +210,7 @@ def main():
     ms_graph = float(np.median(graph_ms))
 
     d = sim.diagnostics(0)
+    t_end = d.time
     # one diagnostics call (energies, momentum, Gauss residual) after steps,
     # host clock around the whole call, median of three
     diag_ms = []
@@ -266,6 +275,12 @@ def main():
             "diagnostics_call_ms": float(np.median(diag_ms)),
         },
         "cpu_baseline": cpu,
+        "skip": None if args.skip_strip <= 0 else {
+            "strip_cells": args.skip_strip,
+            "t_end": t_end,
+            "perturbed_fraction_at_end": min(1.0, (args.skip_strip + 2 * spec.c * t_end / spec.dx[0]) / spec.n[0]),
+            "perturbed_fraction_timed_start": min(1.0, (args.skip_strip + 2 * spec.c * (t_end - spec.dt * args.steps * 6) / spec.dx[0]) / spec.n[0]),
+        },
         "check": {"n_nonfinite": d.n_nonfinite, "n_out_of_range": d.n_out_of_range, "n_sorts": d.n_sorts,
                   "field_energy": sum(d.UE) + sum(d.UB)},
     }

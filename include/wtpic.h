@@ -156,7 +156,7 @@ pic_status pic_field_update(pic_ctx *ctx);
 pic_status pic_step(pic_ctx *ctx, int32_t n_steps);
 
 /* n_steps full steps with the diagnostics of one run recorded every
- * diag_every steps (Sec. 3 follows the field energy over time): history[i]
+ * diag_every steps (Sec. 4 follows the field energy over time): history[i]
  * receives pic_diagnostics after step (i + 1) * diag_every, for
  * i < n_steps / diag_every; host array of that many pic_diag, owned by the
  * caller.  Synchronises the stream at each record.  PIC_ERR_ARG if
@@ -168,6 +168,21 @@ pic_status pic_step_diag(pic_ctx *ctx, int32_t n_steps, int32_t diag_every, int3
  * error counters), copied to *out.  Synchronises the stream.  Returns
  * PIC_ERR_NUMERIC if the error counters are nonzero (out is still filled). */
 pic_status pic_diagnostics(pic_ctx *ctx, int32_t run, pic_diag *out);
+
+/* Partially skipped calculation (Sec. 3, "Partially skipping calculation"):
+ * the region perturbed at time t is the set of points closer than c t to the
+ * initially perturbed region A0 (A0 itself at t = 0); outside it a particle
+ * follows pure drift, so its gather, momentum update and current deposit are
+ * skipped and it only moves with its unchanged momentum.  A0 is the closed
+ * box lo[d] <= x_d / dx_d <= hi[d] (cell units, host arrays of 3 doubles,
+ * entries past ndim ignored) repeated periodically; the distance is
+ * Euclidean in physical units, to the nearest periodic image.  t0 is the
+ * time of the next step (t of x^n for the next pic_gather_push_deposit), and
+ * t advances by dt per step.  lo == NULL switches the skip off for the run.
+ * Membership is decided in FP64 from the particle's position at the start of
+ * the step.  Synchronises the stream.  PIC_ERR_ARG unless
+ * 0 <= lo[d] <= hi[d] <= n[d] and t0 >= 0 (all finite). */
+pic_status pic_set_skip_region(pic_ctx *ctx, int32_t run, const double *lo, const double *hi, double t0);
 
 /* Tuning knobs (tile shape in cells, staging margin in cells, sort check
  * cadence in steps).  Any value <= 0 keeps the current choice.  Must be

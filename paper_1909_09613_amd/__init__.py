@@ -31,7 +31,7 @@ EXPORTED = [
     "pic_query_layout", "pic_init", "pic_set_particles", "pic_get_particles", "pic_set_fields",
     "pic_get_fields", "pic_gather_push_deposit", "pic_field_update", "pic_step", "pic_step_diag",
     "pic_diagnostics",
-    "pic_set_tiling", "pic_kernel_timing", "pic_last_error", "pic_destroy", "pic_table_weights",
+    "pic_set_tiling", "pic_set_skip_region", "pic_kernel_timing", "pic_last_error", "pic_destroy", "pic_table_weights",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
             "pic_step_diag": [vp, i32, i32, i32, ctypes.POINTER(pic_diag)],
             "pic_diagnostics": [vp, i32, ctypes.POINTER(pic_diag)],
             "pic_set_tiling": [vp, ctypes.POINTER(i32), i32, i32],
+            "pic_set_skip_region": [vp, i32, dp, dp, ctypes.c_double],
             "pic_kernel_timing": [vp, i32, dp, ctypes.POINTER(i64)],
             "pic_destroy": [vp],
             "pic_table_weights": [i32, i32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32),
@@ -222,6 +223,24 @@ def pic_set_tiling(ctx, tile=(0, 0, 0), margin=0, sort_every=0):
     _check(lib().pic_set_tiling(ctx, t, margin, sort_every), ctx)
 
 
+def pic_set_skip_region(ctx, run, lo=None, hi=None, t0=0.0):
+    """Partially skipped calculation for one run: the box lo..hi (cell
+    units) is the initially perturbed region, t0 the time of the next step;
+    lo=None switches it off."""
+    if lo is None:
+        _check(lib().pic_set_skip_region(ctx, run, None, None, 0.0), ctx)
+        return
+    def pad3(v):
+        out = np.zeros(3)
+        v = np.asarray(v, dtype=np.float64).ravel()
+        out[:len(v)] = v
+        return out
+
+    lo, hi = pad3(lo), pad3(hi)
+    _check(lib().pic_set_skip_region(ctx, run, lo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     hi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t0)), ctx)
+
+
 def pic_kernel_timing(ctx, enable):
     ms = ctypes.c_double()
     n = ctypes.c_int64()
@@ -296,6 +315,9 @@ class Sim:
 
     def step(self, n=1):
         pic_step(self.ctx, n)
+
+    def set_skip_region(self, run, lo=None, hi=None, t0=0.0):
+        pic_set_skip_region(self.ctx, run, lo, hi, t0)
 
     def step_diag(self, n, every, run=0):
         return pic_step_diag(self.ctx, n, every, run)

@@ -17,7 +17,13 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwtpic.so")
 
-SOURCES = ["tables.cpp", "runtime.cpp", "gpd.hip", "sort.hip", "fields.hip"]
+# (source, object name, extra flags): the particle kernel is built once per
+# precision policy, in parallel
+SOURCES = [
+    ("tables.cpp", "tables", []), ("runtime.cpp", "runtime", []),
+    ("gpd.hip", "gpd32", ["-DWTPIC_GPD_POLICY=32"]), ("gpd.hip", "gpd64", ["-DWTPIC_GPD_POLICY=64"]),
+    ("sort.hip", "sort", []), ("fields.hip", "fields", []),
+]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -32,14 +38,14 @@ def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     procs = []
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
+    for src, name, extra in SOURCES:
+        obj = os.path.join(BUILD, name + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        procs.append((name, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:
         out, _ = p.communicate()

@@ -66,6 +66,12 @@ struct RunDev {
   double dxd[3];      // cell sizes
   double Q[2];        // macro charge per species
   double M[2];        // macro mass per species
+  // partially skipped calculation: box A0 in cell units, the time of A0 at
+  // particle-kernel launch skip_l0, and c and dt in FP64 for t
+  double skip_lo[3], skip_hi[3];
+  double skip_t0, cd, dtd;
+  long long skip_l0;
+  int skip_on;
   Tab<Real> Wh[3];    // W_l on the half-integer lattice
   Tab<Real> Wi[3];    // W_l on the integer lattice (charge form factor)
   Tab<Real> T[3];     // T_l (WT) or W_l (MC) on the integer lattice
@@ -93,6 +99,7 @@ struct DevState {
   unsigned long long n_sorts;
   unsigned int groups_done;    // particle-kernel groups that found the queue empty
   unsigned int arrange_done;   // sort arrange groups finished
+  long long gpd_launches;      // particle-kernel launches completed
 };
 
 template <class Real>
@@ -113,6 +120,7 @@ struct GpdArgs {
   int jw[3];             // current window capacity (nodes)
   int guard[3];          // bbox extent above which a re-sort is requested
   int max_groups;        // workgroups launched (persistent, tile queue)
+  int skip;              // some run uses the partially skipped calculation
 };
 
 // Position of a (possibly negative or >= n) lattice index on a periodic axis.

@@ -114,6 +114,71 @@ __device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
+// ---- partially skipped calculation (Sec. 3) ---------------------------------
+// A particle at canonical position x (cell units, [0, n) per axis) lies in
+// the perturbed region at time t when its distance to the box A0 =
+// [lo, hi] (nearest periodic image, Euclidean in physical units) is below
+// c t, or zero (A(0) = A0).  FP64 without contraction: the decision does not
+// depend on how a compiler fuses the arithmetic.
+__device__ __forceinline__ double skip_ct(double t0, long long steps, double dt, double c) {
+#pragma clang fp contract(off)
+  const double t = t0 + (double)steps * dt;
+  return c * t;
+}
+
+template <int DIM, class Real>
+__device__ __forceinline__ bool skip_perturbed(const RunDev<Real>& R, const double* x, double ct) {
+#pragma clang fp contract(off)
+  double r2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double n = (double)R.n[d];
+    double best = __builtin_huge_val();
+#pragma unroll
+    for (int k = -1; k <= 1; ++k) {
+      const double a = R.skip_lo[d] + k * n, b = R.skip_hi[d] + k * n;
+      double sd = 0.0;
+      if (x[d] < a) sd = a - x[d];
+      else if (x[d] > b) sd = x[d] - b;
+      best = sd < best ? sd : best;
+    }
+    const double sd = best * R.dxd[d];
+    r2 = r2 + sd * sd;
+  }
+  return r2 == 0.0 || r2 < ct * ct;
+}
+
+// Nearest-image distance along one axis for any x in (-3n, 4n).
+__device__ __forceinline__ double skip_axis_any(double x, double lo, double hi, double n) {
+  double best = __builtin_huge_val();
+  for (int k = -3; k <= 3; ++k) {
+    const double a = lo + k * n, b = hi + k * n;
+    const double sd = x < a ? a - x : (x > b ? x - b : 0.0);
+    best = fmin(best, sd);
+  }
+  return best;
+}
+
+// Smallest and largest nearest-image distance along one axis over x in
+// [a, b]: the gap to the nearest image, and the larger end value unless the
+// point halfway round the axis from the box lies inside (then half the
+// complement of the box).
+__device__ __forceinline__ void skip_axis_range(double a, double b, double lo, double hi, double n, double& dmin,
+                                                double& dmax) {
+  dmin = __builtin_huge_val();
+  for (int k = -3; k <= 3; ++k) dmin = fmin(dmin, fmax(0.0, fmax(lo + k * n - b, a - (hi + k * n))));
+  const double far = 0.5 * (n - (hi - lo));
+  if (b - a >= n) {
+    dmax = far;
+    return;
+  }
+  dmax = fmax(skip_axis_any(a, lo, hi, n), skip_axis_any(b, lo, hi, n));
+  for (int k = -3; k <= 3; ++k) {
+    const double pm = hi + far + k * n;
+    if (pm >= a && pm <= b) dmax = far;
+  }
+}
+
 }  // namespace
 
 // Workgroup size of the particle kernel: 2D tiles hold more particles.
@@ -122,7 +187,7 @@ constexpr int gpd_block() {
   return DIM == 2 ? 512 : 256;
 }
 
-template <class P, int L, int DIM, int KT>
+template <class P, int L, int DIM, int KT, bool SKIP>
 __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
                                          const RunDev<typename P::Real>* __restrict__ runs,
                                          const int* __restrict__ tile_run, const int g,
@@ -167,6 +232,32 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       atomicOr(&A.st->sort_request, 1);
     }
     return;
+  }
+
+  // partially skipped calculation: 0 every particle of the tile steps, 1
+  // every one drifts, 2 decided per particle.  The classification bounds the
+  // distance over the box of the particles' cells, with a relative margin so
+  // that it never contradicts the per-particle decision.
+  int smode = 0;
+  double ct = 0.0;
+  if (SKIP && R.skip_on) {
+    ct = skip_ct(R.skip_t0, (long long)A.st->gpd_launches - R.skip_l0, R.dtd, R.cd);
+    double rmin2 = 0.0, rmax2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      double dmin, dmax;
+      skip_axis_range((double)(org[d] + bb[2 * d]), (double)(org[d] + bb[2 * d + 1] + 1), R.skip_lo[d],
+                      R.skip_hi[d], (double)R.n[d], dmin, dmax);
+      rmin2 += (dmin * R.dxd[d]) * (dmin * R.dxd[d]);
+      rmax2 += (dmax * R.dxd[d]) * (dmax * R.dxd[d]);
+    }
+    const double c2 = ct * ct;
+    if (rmax2 == 0.0 || rmax2 < c2 * (1.0 - 1e-9))
+      smode = 0;
+    else if (rmin2 > c2 * (1.0 + 1e-9) + 1e-300)
+      smode = 1;
+    else
+      smode = 2;
   }
 
   const int fwx = A.fw[0], fwy = A.fw[1];
@@ -242,7 +333,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   int* Cw = Qc + 3 * jcap;
 
   // ---- stage E, B on the window; clear the current tile ------------------
-  const int nfs = fs[0] * fs[1] * fs[2];
+  const int nfs = (smode == 1) ? 0 : fs[0] * fs[1] * fs[2];
   for (int i = tid; i < nfs; i += nth) {
     const int w0 = i % fs[0];
     const int q = i / fs[0];
@@ -306,7 +397,117 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     jws[d] = pin(d == 0 ? 1 : (d == 1 ? A.jw[0] : A.jw[0] * A.jw[1]));
   }
 
-  for (int p = sA + tid; p < sC; p += nth) {
+  // partially skipped calculation: outside the perturbed region a particle
+  // follows pure drift -- it keeps its momentum, moves with that momentum's
+  // velocity (the arithmetic of the move in the loop below) and deposits no
+  // current; it still counts for the box, the cell counts and the next
+  // step's fixed-point bounds
+  auto drift = [&](int p, const int* c, const Real* f, const Real* xo, Real u0, Real u1, Real u2, const int* rel) {
+    const Real ig = fast_rsqrt(Real(1) + u0 * u0 + u1 * u1 + u2 * u2);
+    const Real vd[3] = {u0 * ig, u1 * ig, u2 * ig};
+    int cwi = 0, cw[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const Real step = R.a[d] * vd[d];
+      int cnd;
+      Real ddd;
+      if (P::kAbs) {
+        const Real xn = xo[d] + step;
+        cnd = (int)floor(xn);
+        ddd = xn - xo[d];
+        Real w = xn;
+        const Real nd = Real(R.n[d]);
+        while (w < Real(0)) w += nd;
+        while (w >= nd) w -= nd;
+        B.pos[d][p] = w;
+      } else {
+        Real t = f[d] + step;
+        int dc = 0;
+        if (t >= Real(1)) {
+          t -= Real(1);
+          dc = 1;
+        } else if (t < Real(0)) {
+          t += Real(1);
+          dc = -1;
+          if (t >= Real(1)) {
+            t = Real(0);
+            dc = 0;
+          }
+        }
+        cnd = c[d] + dc;
+        ddd = (t - f[d]) + Real(dc);
+        B.pos[d][p] = t;
+        int m = cnd;
+        if (m < 0) m += R.n[d];
+        else if (m >= R.n[d]) m -= R.n[d];
+        cw[d] = m;
+      }
+      // a drifting particle still bounds the next step's fixed-point scale
+      if (kFix) mnew[d] = fmax(mnew[d], fabs(ddd));
+      const int rn = rel[d] + (cnd - c[d]);
+      bmin[d] = min(bmin[d], rn);
+      bmax[d] = max(bmax[d], rn);
+      cwi += (rn - jo_[d]) * jws[d];
+    }
+    if (kFix && DIM == 2) mnew[2] = fmax(mnew[2], fabs(vd[2]));
+    if (kFix) atomicAdd(Cw + cwi, 1);
+    if (!P::kAbs) B.cell[p] = pack_cell<DIM>(cw[0], cw[1], cw[2]);
+  };
+  if (SKIP && smode == 1) {
+    // every particle of the tile drifts: several particles per thread with
+    // their loads issued together (this loop is bound by memory latency)
+    constexpr int U = 4;
+    for (int p0 = sA + tid; p0 < sC; p0 += U * nth) {
+      int cc[U][3];
+      Real ff[U][3], xx[U][3], uu[U][3];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int p = min(p0 + k * nth, sC - 1);
+        cc[k][0] = cc[k][1] = cc[k][2] = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ff[k][d] = xx[k][d] = Real(0);
+        if (P::kAbs) {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) xx[k][d] = B.pos[d][p];
+        } else {
+          unpack_cell<DIM>(B.cell[p], cc[k][0], cc[k][1], cc[k][2]);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) ff[k][d] = B.pos[d][p];
+        }
+        uu[k][0] = B.u[0][p];
+        uu[k][1] = B.u[1][p];
+        uu[k][2] = B.u[2][p];
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int p = p0 + k * nth;
+        if (p >= sC) break;
+        if (P::kAbs) {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            const Real fl = floor(xx[k][d]);
+            cc[k][d] = (int)fl;
+            ff[k][d] = xx[k][d] - fl;
+          }
+        }
+        int rel[3] = {0, 0, 0};
+        bool inwin = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const int rr = wrap_near(cc[k][d] - co[d], nn[d]) + lo_[d];
+          rel[d] = rr;
+          inwin = inwin && rr >= rlo[d] && rr <= rhi[d];
+        }
+        if (!inwin) {
+          ++noor;
+          continue;
+        }
+        drift(p, cc[k], ff[k], xx[k], uu[k][0], uu[k][1], uu[k][2], rel);
+      }
+    }
+  }
+
+  for (int p = (SKIP && smode == 1) ? sC : sA + tid; p < sC; p += nth) {
     const int sp = (p >= sB) ? 1 : 0;
     // ---- load ---------------------------------------------------------
     int c[3] = {0, 0, 0};
@@ -344,6 +545,19 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (!inwin) {
       ++noor;
       continue;
+    }
+    if constexpr (SKIP) {
+      bool drifting = smode == 1;
+      if (smode == 2) {
+        double xa[3];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xa[d] = P::kAbs ? (double)xo[d] : (double)c[d] + (double)f[d];
+        drifting = !skip_perturbed<DIM>(R, xa, ct);
+      }
+      if (drifting) {
+        drift(p, c, f, xo, u0, u1, u2, rel);
+        continue;
+      }
     }
 
     // ---- weights at x^n --------------------------------------------------
@@ -736,7 +950,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 
   // ---- flush the current tile ------------------------------------------------
   double* Jg = A.J + R.cell0;
-  const int njs = jsz[0] * jsz[1] * jsz[2];
+  const int njs = (smode == 1) ? 0 : jsz[0] * jsz[1] * jsz[2];
   for (int i = tid; i < njs; i += nth) {
     const int w0 = i % jsz[0];
     const int q = i / jsz[0];
@@ -790,9 +1004,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 // Persistent workgroups: each takes tiles from a device queue until none are
 // left, so uneven tiles (edge tiles, runs of different size) balance.  The
 // queue starts at zero (set at initialisation, then rewound by the last
-// group of every launch).
-template <class P, int L, int DIM>
-__global__ void __launch_bounds__(gpd_block<DIM>())
+// group of every launch).  The variant with the partially skipped
+// calculation is held to four waves per SIMD (two 2D workgroups per CU):
+// left alone it takes ~10 more registers than the plain kernel and drops to
+// three, which costs far more than the few spilled values.
+template <class P, int L, int DIM, bool SKIP>
+__global__ void __launch_bounds__(gpd_block<DIM>()) __attribute__((amdgpu_waves_per_eu(SKIP ? 4 : 1)))
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
                const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
@@ -809,14 +1026,15 @@ __global__ void __launch_bounds__(gpd_block<DIM>())
       if (threadIdx.x == 0 && atomicAdd(&A.st->groups_done, 1u) == gridDim.x - 1) {
         A.st->tile_queue = 0;
         A.st->groups_done = 0;
+        A.st->gpd_launches += 1;
       }
       return;
     }
     const int kt = runs[tile_run[g]].KT;
     if (kt == L + 1)
-      gpd_tile<P, L, DIM, L + 1>(A, runs, tile_run, g, lds_dyn, sred);
+      gpd_tile<P, L, DIM, L + 1, SKIP>(A, runs, tile_run, g, lds_dyn, sred);
     else
-      gpd_tile<P, L, DIM, L + 2>(A, runs, tile_run, g, lds_dyn, sred);
+      gpd_tile<P, L, DIM, L + 2, SKIP>(A, runs, tile_run, g, lds_dyn, sred);
     __syncthreads();
   }
 }
@@ -824,7 +1042,14 @@ __global__ void __launch_bounds__(gpd_block<DIM>())
 template <class P, int L, int DIM>
 static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
   const int grid = a.G < a.max_groups ? a.G : a.max_groups;
-  hipLaunchKernelGGL((gpd_kernel<P, L, DIM>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs, a.tile_run);
+  // the variant with the partially skipped calculation only where a run uses
+  // it (its extra registers would cost the plain step occupancy)
+  if (a.skip)
+    hipLaunchKernelGGL((gpd_kernel<P, L, DIM, true>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs,
+                       a.tile_run);
+  else
+    hipLaunchKernelGGL((gpd_kernel<P, L, DIM, false>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs,
+                       a.tile_run);
   return hipGetLastError();
 }
 
@@ -977,9 +1202,6 @@ hipError_t launch_rho_tiles(const GpdArgs<typename P::Real>& a, int run, int nti
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_rho_tiles<F32>(const GpdArgs<float>&, int, int, double*, int, int, size_t, hipStream_t);
-template hipError_t launch_rho_tiles<F64>(const GpdArgs<double>&, int, int, double*, int, int, size_t, hipStream_t);
-
 template <class P>
 hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, size_t lds, hipStream_t s) {
   if (ndim == 2) {
@@ -1000,7 +1222,15 @@ hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, s
   return hipErrorInvalidValue;
 }
 
+// Each precision policy can be built as a translation unit of its own
+// (WTPIC_GPD_POLICY = 32 or 64), so that the two compile in parallel.
+#if !defined(WTPIC_GPD_POLICY) || WTPIC_GPD_POLICY == 32
 template hipError_t launch_gpd<F32>(const GpdArgs<float>&, int, int, size_t, hipStream_t);
+template hipError_t launch_rho_tiles<F32>(const GpdArgs<float>&, int, int, double*, int, int, size_t, hipStream_t);
+#endif
+#if !defined(WTPIC_GPD_POLICY) || WTPIC_GPD_POLICY == 64
 template hipError_t launch_gpd<F64>(const GpdArgs<double>&, int, int, size_t, hipStream_t);
+template hipError_t launch_rho_tiles<F64>(const GpdArgs<double>&, int, int, double*, int, int, size_t, hipStream_t);
+#endif
 
 }  // namespace wtpic

@@ -38,6 +38,10 @@ struct RunHost {
   int ntiles;
   double dt;
   bool set[2];
+  // partially skipped calculation (pic_set_skip_region)
+  bool skip_on;
+  double skip_lo[3], skip_hi[3], skip_t0;
+  long long skip_l0;
 };
 
 // Offsets of every array inside the four caller buffers.
@@ -321,6 +325,15 @@ pic_status build_runs(pic_ctx* c, std::vector<RunDev<Real>>& out) {
         R.m4beta[k][e2] = Real(coef);
       }
     }
+    R.skip_on = H.skip_on ? 1 : 0;
+    for (int k = 0; k < 3; ++k) {
+      R.skip_lo[k] = H.skip_lo[k];
+      R.skip_hi[k] = H.skip_hi[k];
+    }
+    R.skip_t0 = H.skip_t0;
+    R.skip_l0 = H.skip_l0;
+    R.cd = d.c;
+    R.dtd = H.dt;
     for (int s = 0; s < 2; ++s) {
       const double Q = d.macro_charge[s], qm = d.q_over_m[s];
       R.eps[s] = Real(qm * H.dt / (2.0 * d.c));
@@ -331,6 +344,18 @@ pic_status build_runs(pic_ctx* c, std::vector<RunDev<Real>>& out) {
     }
   }
   return PIC_OK;
+}
+
+// Rebuilds the per-run device table from the host state (tiling unchanged).
+template <class Real>
+pic_status upload_runs(pic_ctx* c) {
+  std::vector<RunDev<Real>> rd;
+  pic_status st = build_runs<Real>(c, rd);
+  if (st != PIC_OK) return st;
+  hipError_t e = host_copy(c, c->S + c->lay.s_runs, rd.data(), sizeof(RunDev<Real>) * rd.size(),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return c->hip(e, "run table upload");
 }
 
 // Tiling-dependent state: tiles per run, windows, guard, LDS size, and the
@@ -436,6 +461,8 @@ GpdArgs<Real> gpd_args(pic_ctx* c) {
   a.ncell_total = c->ncell_total;
   a.G = c->G;
   a.max_groups = c->max_groups;
+  a.skip = 0;
+  for (const RunHost& H : c->runs) a.skip |= H.skip_on ? 1 : 0;
   for (int k = 0; k < 3; ++k) {
     a.tile[k] = c->tile[k];
     a.fw[k] = c->fw[k];
@@ -863,6 +890,39 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
   }
   *out = c;
   return PIC_OK;
+}
+
+pic_status pic_set_skip_region(pic_ctx* c, int32_t run, const double* lo, const double* hi, double t0) {
+  if (!c) return PIC_ERR_ARG;
+  if (run < 0 || run >= c->nruns) return c->fail(PIC_ERR_ARG, "run out of range");
+  RunHost& H = c->runs[run];
+  RunHost keep = H;
+  if (!lo) {
+    H.skip_on = false;
+  } else {
+    if (!hi) return c->fail(PIC_ERR_ARG, "hi is NULL");
+    if (!(t0 >= 0.0) || !std::isfinite(t0)) return c->fail(PIC_ERR_ARG, "t0 must be finite and >= 0");
+    for (int k = 0; k < c->ndim; ++k)
+      if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(lo[k] >= 0.0) || !(lo[k] <= hi[k]) ||
+          !(hi[k] <= (double)H.n[k]))
+        return c->fail(PIC_ERR_ARG, "skip box needs 0 <= lo <= hi <= n on every axis");
+    H.skip_on = true;
+    for (int k = 0; k < 3; ++k) {
+      H.skip_lo[k] = k < c->ndim ? lo[k] : 0.0;
+      H.skip_hi[k] = k < c->ndim ? hi[k] : 0.0;
+    }
+    H.skip_t0 = t0;
+    H.skip_l0 = c->step;  // launches enqueued so far: the next one is at t0
+  }
+  pic_status st = c->f64() ? upload_runs<double>(c) : upload_runs<float>(c);
+  if (st != PIC_OK) {
+    std::string e = c->err;
+    H = keep;
+    (void)(c->f64() ? upload_runs<double>(c) : upload_runs<float>(c));
+    c->err = e;
+  }
+  drop_graph(c);  // the step graph holds the kernel variant
+  return st;
 }
 
 pic_status pic_set_tiling(pic_ctx* c, const int32_t tile[3], int32_t margin, int32_t sort_every) {

@@ -1,6 +1,6 @@
 """Multi-step physics of the GPU path: the numerical Cherenkov instability
 (NCI) of a drifting pair plasma, the quantity the WT scheme exists to
-suppress (Sec. 3, Fig. 1).  The paper prints no growth-rate table, so the
+suppress (Sec. 4, Fig. 1).  The paper prints no growth-rate table, so the
 absolute rates are parity unpinned; what is tested is what the paper states
 qualitatively, plus the FP32 path against the FP64 path:
 
