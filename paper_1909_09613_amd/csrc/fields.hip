@@ -168,7 +168,7 @@ template hipError_t launch_fill<int>(int*, long long, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // Diagnostics (FP64).  acc: [0..2] sum E_d^2, [3..5] sum B_d^2, [6..7] sum
 // M (gamma-1) c^2 per species, [8..10] sum M u c, [11] max |D.E - rho| (bits).
-// The sums are taken per block into part[block][16] and then added block by
+// The sums are taken per block into part[c][block] and then added block by
 // block in a fixed order, so that repeated diagnostics of one state agree
 // to the last bit.
 // ---------------------------------------------------------------------------
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) diag_fields_kernel(DiagArgs<Real> A, long
   }
   for (int c = 0; c < 6; ++c) {
     const double t = block_sum(s[c], sh);
-    if (threadIdx.x == 0) A.part[16 * blockIdx.x + c] = t;
+    if (threadIdx.x == 0) A.part[c * kDiagBlocks + blockIdx.x] = t;
   }
 }
 
@@ -232,18 +232,18 @@ __global__ void __launch_bounds__(256) diag_particles_kernel(DiagArgs<typename P
   }
   for (int c = 0; c < 5; ++c) {
     const double t = block_sum(s[c], sh);
-    if (threadIdx.x == 0) A.part[16 * blockIdx.x + 6 + c] = t;
+    if (threadIdx.x == 0) A.part[(6 + c) * kDiagBlocks + blockIdx.x] = t;
   }
 }
 
-// acc[c] = sum over blocks of part[block][c]: the field sums over nbf
+// acc[c] = sum over blocks of part[c][block]: the field sums over nbf
 // blocks, the particle sums over nbp blocks; one wave per accumulator, each
 // lane a fixed stride of blocks, then a fixed butterfly.
 __global__ void __launch_bounds__(704) diag_final_kernel(double* acc, const double* part, int nbf, int nbp) {
   const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nb = (c < 6) ? nbf : nbp;
   double s = 0.0;
-  for (int b = lane; b < nb; b += 64) s += part[16 * b + c];
+  for (int b = lane; b < nb; b += 64) s += part[c * kDiagBlocks + b];
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) acc[c] = s;
 }
@@ -300,7 +300,7 @@ __global__ void diag_rho_kernel(DiagArgs<typename P::Real> A, long long p0, long
 }
 
 template <class Real, int DIM>
-__global__ void diag_gauss_kernel(DiagArgs<Real> A, long long cells) {
+__global__ void __launch_bounds__(256) diag_gauss_kernel(DiagArgs<Real> A, long long cells) {
   const RunDev<Real>& R = A.runs[A.run];
   const Real* F = A.F + R.cell0;
   const long long NT = A.ncell_total;
@@ -315,9 +315,9 @@ __global__ void diag_gauss_kernel(DiagArgs<Real> A, long long cells) {
     const int k = ci / nxy;
     double div = 0.0;
     for (int d = 0; d < DIM; ++d) {
-      const int pi = (d == 0) ? wrapi(i - 1, R.n[0]) : i;
-      const int pj = (d == 1) ? wrapi(j - 1, R.n[1]) : j;
-      const int pk = (d == 2) ? wrapi(k - 1, R.n[2]) : k;
+      const int pi = (d == 0) ? (i == 0 ? R.n[0] - 1 : i - 1) : i;
+      const int pj = (d == 1) ? (j == 0 ? R.n[1] - 1 : j - 1) : j;
+      const int pk = (d == 2) ? (k == 0 ? R.n[2] - 1 : k - 1) : k;
       const long long pc = pi + (long long)R.n[0] * (pj + (long long)R.n[1] * pk);
       div += ((double)F[d * NT + ci] - (double)F[d * NT + pc]) / R.dxd[d];
     }
@@ -328,7 +328,14 @@ __global__ void diag_gauss_kernel(DiagArgs<Real> A, long long cells) {
     const double o = __shfl_xor(mx, off);
     mx = o > mx ? o : mx;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned long long*>(&A.acc[11]), __double_as_longlong(mx));
+  // one atomic per block (a maximum is exact in any order)
+  __shared__ double wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = wmax[w] > mx ? wmax[w] : mx;
+    atomicMax(reinterpret_cast<unsigned long long*>(&A.acc[11]), __double_as_longlong(mx));
+  }
 }
 
 template <class P>

@@ -4,7 +4,8 @@ time t (points closer than c t to the box A0) a particle only drifts.
 
   * one step from identical state with a box whose perturbed region covers
     some tiles completely, misses others and cuts through the rest (the three
-    tile classes of the kernel), FP64 and mixed precision;
+    tile classes of the kernel), FP64 and mixed precision, 2D and 3D (with
+    anisotropic cells);
   * 20 FP64 steps from t = 0 with the region growing, against the oracle's
     stepping with t = t0 + n dt;
   * two runs in one context, one with the skip and one without, and the skip
@@ -82,6 +83,53 @@ def test_skip_one_step(orc, precision):
     assert ex <= tol_x and eu <= tol_x
     for k in range(3):
         assert scale[k] > 0
+        assert ej[k] <= H.current_tol(spec, k, fp32)
+
+
+@pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32], ids=["fp64", "fp32"])
+def test_skip_one_step_3d(orc, precision):
+    """3D with anisotropic cells: the distance is Euclidean in physical units."""
+    fp32 = precision == wt.PIC_MIXED32
+    spec = RunSpec(3, (32, 24, 20), 2, 0.4, 50.0, 0.01, 2, 906, dx=(1.0, 0.8, 1.25))
+    sp, E, B = H.random_state(spec, 10, fp32=fp32)
+    lo = np.array([12.0, 8.0, 6.0])
+    hi = np.array([16.0, 12.5, 9.0])
+    t0 = 5.0
+    g = H.oracle_grid(orc, spec)
+    g.E[:] = E
+    g.B[:] = B
+    assert _margin_ok(orc, g, sp, lo, hi, t0)
+    inside = [g.perturbed(s["x"], lo, hi, t0).astype(bool) for s in sp]
+    frac = np.mean(np.concatenate(inside))
+    assert 0.1 < frac < 0.7
+    parts = []
+    ref = H.copy_species(sp)
+    for s in ref:
+        g.zero_J()
+        g.push_species(s["x"], s["u"], s["qm"], s["Q"], skip=(lo, hi, t0))
+        parts.append(g.J.copy())
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, sp)
+        sim.set_fields(0, E, B)
+        sim.set_skip_region(0, lo, hi, t0)
+        sim.gpd()
+        got = [sim.particles(0, s) for s in range(2)]
+        _, _, J = sim.fields(0)
+        d = sim.diagnostics(0)
+    finally:
+        sim.close()
+    assert d.n_nonfinite == 0 and d.n_out_of_range == 0
+    for s in range(2):
+        assert np.array_equal(got[s][1][~inside[s]], sp[s]["u"][~inside[s]])
+    ex, eu = H.particle_errors(spec, ref, got)
+    scale = np.max(np.abs(parts[0]) + np.abs(parts[1]), axis=1)
+    ej = [float(np.max(np.abs(J[k] - parts[0][k] - parts[1][k])) / scale[k]) for k in range(3)]
+    print("skip one step 3D %s: inside %.2f dx=%.2e du=%.2e dJ=%s" % (
+        "fp32" if fp32 else "fp64", frac, ex, eu, ["%.2e" % v for v in ej]), flush=True)
+    tol_x = 2e-6 if fp32 else 1e-12
+    assert ex <= tol_x and eu <= tol_x
+    for k in range(3):
         assert ej[k] <= H.current_tol(spec, k, fp32)
 
 
