@@ -284,6 +284,10 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // windows whose quantum uses the a-priori bound m_c < a_c (|v| < c; 1 for
   // v3 in 2D), coarse but safe for any particle.
   constexpr bool kFix = !P::kAbs;
+  // cell counts (the (l+3)^d cmax bound) only in 2D: a 3D tile holds fewer
+  // particles than (l+3)^3 times its densest cell, so its bound is the tile's
+  // particle count, and the LDS the counts would take buys 3D tiles room
+  constexpr bool kCnt = kFix && DIM == 2;
   Real qinv[3] = {Real(0), Real(0), Real(0)}, thr[3] = {Real(0), Real(0), Real(0)};
   Real qcinv[3] = {Real(0), Real(0), Real(0)};
   double qd[3] = {0.0, 0.0, 0.0}, qcd[3] = {0.0, 0.0, 0.0};
@@ -326,8 +330,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     F6 = reinterpret_cast<Real*>(lds);
     Jl = reinterpret_cast<Acc*>(F6 + 6 * fcap);
   }
-  // fixed-point path: 3 fine and 3 coarse int windows, then the particle
-  // count per cell
+  // fixed-point path: 3 fine and 3 coarse int windows, then (2D) the
+  // particle count per cell
   int* Qf = reinterpret_cast<int*>(Jl);
   int* Qc = Qf + 3 * jcap;
   int* Cw = Qc + 3 * jcap;
@@ -360,7 +364,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     }
   }
   if (kFix) {
-    for (int i = tid; i < 7 * jcap; i += nth) Qf[i] = 0;
+    for (int i = tid; i < (kCnt ? 7 : 6) * jcap; i += nth) Qf[i] = 0;
   } else {
     for (int i = tid; i < 3 * jcap; i += nth) Jl[i] = Acc(0);
   }
@@ -450,7 +454,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       cwi += (rn - jo_[d]) * jws[d];
     }
     if (kFix && DIM == 2) mnew[2] = fmax(mnew[2], fabs(vd[2]));
-    if (kFix) atomicAdd(Cw + cwi, 1);
+    if (kCnt) atomicAdd(Cw + cwi, 1);
     if (!P::kAbs) B.cell[p] = pack_cell<DIM>(cw[0], cw[1], cw[2]);
   };
   if (SKIP && smode == 1) {
@@ -651,7 +655,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         bmax[d] = max(bmax[d], rel[d]);
         cwi += (rel[d] - jo_[d]) * jws[d];
       }
-      if (kFix) atomicAdd(Cw + cwi, 1);
+      if (kCnt) atomicAdd(Cw + cwi, 1);
       continue;
     }
     u0 = n0;
@@ -885,7 +889,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       bmax[d] = max(bmax[d], rn);
       cwi += (rn - jo_[d]) * jws[d];
     }
-    if (kFix) atomicAdd(Cw + cwi, 1);
+    if (kCnt) atomicAdd(Cw + cwi, 1);
     if (P::kAbs) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) B.pos[d][p] = xw[d];
@@ -938,7 +942,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     }
   }
   __syncthreads();
-  if (kFix) {
+  if (kCnt) {
     // largest particle count of one cell at the new positions (particles
     // left in place by a non-finite push are counted at their cell)
     int cm = 0;
@@ -969,7 +973,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     }
   }
 
-  if (kFix) __syncthreads();
+  if (kCnt) __syncthreads();
   if (tid == 0) {
     bool need = false;
     for (int d = 0; d < 3; ++d) {
@@ -994,7 +998,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (need) atomicOr(&A.st->sort_request, 1);
     if (kFix) {
       for (int c = 0; c < 3; ++c) A.jb[4 * g + c] = __int_as_float(sred[8 + c]);
-      A.jb[4 * g + 3] = (float)sred[11];
+      A.jb[4 * g + 3] = kCnt ? (float)sred[11] : 3.0e38f;  // 3D: the tile count bounds
     }
     if (sred[6]) atomicAdd(&A.st->n_nonfinite, (unsigned long long)sred[6]);
     if (sred[7]) atomicAdd(&A.st->n_out_of_range, (unsigned long long)sred[7]);
@@ -1042,6 +1046,14 @@ __global__ void __launch_bounds__(gpd_block<DIM>()) __attribute__((amdgpu_waves_
 template <class P, int L, int DIM>
 static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
   const int grid = a.G < a.max_groups ? a.G : a.max_groups;
+  if (lds > 64 * 1024) {
+    // more than the default dynamic LDS of a launch (explicit large tiles)
+    const hipError_t e = a.skip ? hipFuncSetAttribute(reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, true>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                                : hipFuncSetAttribute(reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, false>),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   // the variant with the partially skipped calculation only where a run uses
   // it (its extra registers would cost the plain step occupancy)
   if (a.skip)

@@ -20,7 +20,11 @@ thread_local std::string g_err = "no error";
 
 // smallest tile edge; bounds the scratch layout
 int min_tile(int ndim) { return ndim == 2 ? 4 : 2; }
-constexpr int kMaxLds = 64 * 1024; // per-workgroup LDS budget of the particle kernel
+constexpr int kMaxLds = 160 * 1024;     // LDS of a gfx950 CU: the most one workgroup can take
+// budget of the default tile choice: half a CU's LDS, so that two groups
+// share a CU (measured in 3D: 8x4x4 FP32 tiles at 69 KB and 4x4x4 FP64 tiles
+// at 67 KB beat the smaller tiles that fit 64 KB by 8% and 15%)
+constexpr int kDefaultLds = 80 * 1024;
 constexpr int kMaxTileCells = 4096; // the sort orders a tile's cells in LDS
 constexpr size_t kAlign = 256;
 
@@ -405,9 +409,9 @@ pic_status apply_tiling(pic_ctx* c) {
   const size_t fcap = (size_t)c->fw[0] * c->fw[1] * c->fw[2];
   const size_t jcap = (size_t)c->jw[0] * c->jw[1] * c->jw[2];
   const size_t rs = sizeof(Real);
-  // FP32: fine and coarse fixed-point current windows and a cell count
-  // (7 ints per node); FP64: FP64 current windows
-  c->lds = 6 * rs * fcap + (c->f64() ? 3 * sizeof(double) : 7 * sizeof(int)) * jcap;
+  // FP32: fine and coarse fixed-point current windows and, in 2D, a cell
+  // count (7 or 6 ints per node); FP64: FP64 current windows
+  c->lds = 6 * rs * fcap + (c->f64() ? 3 * sizeof(double) : (nd == 2 ? 7 : 6) * sizeof(int)) * jcap;
   if (c->lds > (size_t)c->lds_budget) return c->fail(PIC_ERR_ARG, "tile and margin need more LDS than the workgroup budget");
   // device tables
   c->tile_run_host.assign(G, 0);
@@ -877,11 +881,14 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
   c->margin = (c->ndim == 2) ? 3 : 2;
   c->sort_every = (c->ndim == 2) ? 2 : 1;
   st = PIC_ERR_ARG;
+  const size_t full = c->lds_budget;
+  c->lds_budget = std::min(full, (size_t)kDefaultLds);
   for (int i = 0; i < ncand && st != PIC_OK; ++i) {
     const int* t = (c->ndim == 2) ? cand2[i] : cand3[i];
     for (int k = 0; k < 3; ++k) c->tile[k] = t[k];
     st = c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c);
   }
+  c->lds_budget = full;  // an explicit tiling may take up to the whole LDS
   if (st == PIC_OK) st = c->f64() ? upload_static<double>(c) : upload_static<float>(c);
   if (st != PIC_OK) {
     g_err = c->err;
