@@ -873,11 +873,14 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
       c->max_groups = 8 * cus;  // more than fit at once; the extra ones find the queue empty
   }
-  // 16 x 16 measured fastest in 2D at both precisions (a wider tile stages
-  // more fields per particle than it saves in window overlap)
-  static const int cand2[][3] = {{16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}};
+  // measured in 2D (1024x512 cubic; 64 batched runs; 4096x2048): FP32 is
+  // fastest with 32 x 16 tiles (7%, 13% and 2% ahead of 16 x 16; 32 x 32
+  // and 64 x 16 need more than half the LDS), FP64 with 16 x 16
+  static const int cand2s[][3] = {{32, 16, 1}, {16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}};
+  static const int cand2d[][3] = {{16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}, {4, 4, 1}};
   static const int cand3[][3] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}};
-  const int ncand = (c->ndim == 2) ? 5 : 6;
+  const int (*cand2)[3] = c->f64() ? cand2d : cand2s;
+  const int ncand = 6;
   c->margin = (c->ndim == 2) ? 3 : 2;
   c->sort_every = (c->ndim == 2) ? 2 : 1;
   st = PIC_ERR_ARG;
