@@ -1009,11 +1009,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 // left, so uneven tiles (edge tiles, runs of different size) balance.  The
 // queue starts at zero (set at initialisation, then rewound by the last
 // group of every launch).  The variant with the partially skipped
-// calculation is held to four waves per SIMD (two 2D workgroups per CU):
-// left alone it takes ~10 more registers than the plain kernel and drops to
-// three, which costs far more than the few spilled values.
+// calculation is held to the plain kernel's occupancy (2D: four waves per
+// SIMD, two workgroups per CU; 3D: three): left alone it takes ~10 more
+// registers and drops a wave, which costs far more than the few spilled
+// values.
 template <class P, int L, int DIM, bool SKIP>
-__global__ void __launch_bounds__(gpd_block<DIM>()) __attribute__((amdgpu_waves_per_eu(SKIP ? 4 : 1)))
+__global__ void __launch_bounds__(gpd_block<DIM>())
+__attribute__((amdgpu_waves_per_eu(SKIP ? (DIM == 2 ? 4 : 3) : 1)))
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
                const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
