@@ -185,10 +185,12 @@ pic_status pic_diagnostics(pic_ctx *ctx, int32_t run, pic_diag *out);
 pic_status pic_set_skip_region(pic_ctx *ctx, int32_t run, const double *lo, const double *hi, double t0);
 
 /* Tuning knobs (tile shape in cells, staging margin in cells, sort check
- * cadence in steps).  Any value <= 0 keeps the current choice.  Must be
+ * cadence in steps).  Any value <= 0 keeps the current choice (by default
+ * the first of a measured list of tile shapes whose LDS fits half a CU: 2D
+ * 32x16 in mixed precision, 16x16 in FP64; 3D 8x4x4 and 4x4x4).  Must be
  * called before the first step; returns PIC_ERR_STATE afterwards, and
- * PIC_ERR_ARG if the windows need more LDS than a workgroup has, if margin
- * <= sort_every, or if a tile has more than 4096 cells. */
+ * PIC_ERR_ARG if the windows need more LDS than a workgroup can have
+ * (160 KB), if margin <= sort_every, or if a tile has more than 4096 cells. */
 pic_status pic_set_tiling(pic_ctx *ctx, const int32_t tile[3], int32_t margin, int32_t sort_every);
 
 /* Device timing of the gather-push-deposit kernel.  enable != 0 starts

@@ -9,11 +9,11 @@
 namespace wtpic {
 
 // Precision policies.  F32: int32 cell + FP32 offsets, FP32 momenta, fields
-// and weights; per-tile and global current FP64.  F64: absolute FP64
-// positions, FP64 everywhere.
+// and weights; per-tile current in 32-bit fixed point (integer LDS atomics),
+// global current FP64.  F64: absolute FP64 positions, FP64 everywhere.
 struct F32 {
   using Real = float;
-  using Acc = double;  // LDS current tile: ds_add_f64 is ~7x faster than ds_add_f32 on gfx950
+  using Acc = double;  // (unused: the fixed-point windows take the FP64 windows' place in LDS)
   static constexpr bool kAbs = false;
 };
 struct F64 {

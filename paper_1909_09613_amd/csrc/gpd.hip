@@ -865,8 +865,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (!kFix) {
       deposit([&](int c, int i, Real v) { lds_add<Acc>(Jl + c * jcap + i, Acc(v)); }, jx, jy, jz, Real(0));
     } else {
-      // a particle whose step (or |v3|) exceeds the tile's bound takes the
-      // FP64 global path, so that no fixed-point node sum can overflow
+      // a particle whose step (or |v3|) exceeds the tile's bound deposits
+      // into the coarse windows, so that no fine node sum can overflow
       const Real m0 = fabs(dd[0]), m1 = fabs(dd[1]), m2 = (DIM == 2) ? fabs(vv[2]) : fabs(dd[2]);
       mnew[0] = fmax(mnew[0], m0);
       mnew[1] = fmax(mnew[1], m1);
