@@ -29,6 +29,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -65,10 +66,16 @@ def cell_bytes(precision):
 
 
 def source_digest():
+    """Digest of the particle kernel's sources with comments and blank space
+    removed: the stored HBM counters stay valid across comment edits and are
+    dropped when code changes."""
     h = hashlib.sha256()
     for name in ("gpd.hip", "common.hpp", "tables.hpp", "runtime.cpp"):
-        with open(os.path.join(ROOT, "paper_1909_09613_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1909_09613_amd", "csrc", name), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
