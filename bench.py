@@ -226,6 +226,16 @@ def main():
         t0 = time.perf_counter()
         sim.diagnostics(0)
         diag_ms.append((time.perf_counter() - t0) * 1e3)
+    # the field update (a8) alone, after the state above was read: B half
+    # step, E step with J, B half step
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sim.stream):
+        start.record(sim.stream)
+        for _ in range(args.steps):
+            sim.field_update()
+        stop.record(sim.stream)
+    stop.synchronize()
+    field_ms = start.elapsed_time(stop) / args.steps
     sim.close()
 
     # the step rate: pic_step replays of the captured step graph (the
@@ -277,6 +287,7 @@ def main():
         "breakdown": {
             "gpd_kernel_ms": gpd_ms,
             "rest_of_step_ms": ms_total / args.steps - gpd_ms,
+            "field_update_ms": field_ms,
             "first_step_with_full_sort_ms": ms_sort_step,
             "sorts_in_timed_region": d.n_sorts - d0.n_sorts,
             "diagnostics_call_ms": float(np.median(diag_ms)),
