@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--precision", default="mixed32", choices=["mixed32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--tile", default=None, help="tile shape, e.g. 32x16")
+    ap.add_argument("--margin", type=int, default=0, help="staging margin in cells (0 = default)")
+    ap.add_argument("--sort-every", type=int, default=0, help="sort check cadence in steps (0 = default)")
     ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5], help="workload")
     ap.add_argument("--skip-strip", type=float, default=0.0,
                     help="partially skipped calculation: initially perturbed strip of this width (cells, "
@@ -147,9 +149,9 @@ def main():
     prec = wt.PIC_FP64 if args.precision == "fp64" else wt.PIC_MIXED32
     t_setup = time.perf_counter()
     sim = wt.Sim(specs, prec)
-    if args.tile:
-        t = [int(v) for v in args.tile.split("x")] + [0]
-        wt.pic_set_tiling(sim.ctx, tuple(t[:3]), 0, 0)
+    if args.tile or args.margin or args.sort_every:
+        t = ([int(v) for v in args.tile.split("x")] if args.tile else []) + [0, 0, 0]
+        wt.pic_set_tiling(sim.ctx, tuple(t[:3]), args.margin, args.sort_every)
     for r, sr in enumerate(specs):
         sim.set_species(r, inputs.make_species(sr))
     if args.skip_strip > 0:
