@@ -100,6 +100,8 @@ struct DevState {
   unsigned int groups_done;    // particle-kernel groups that found the queue empty
   unsigned int arrange_done;   // sort arrange groups finished
   long long gpd_launches;      // particle-kernel launches completed
+  unsigned int count_done;     // sort count groups finished
+  unsigned int pad1;
 };
 
 template <class Real>

@@ -2,10 +2,10 @@
 // particles have outgrown the staging margin of the gather-push-deposit
 // kernel (a device-side request flag; all kernels exit at once otherwise).
 //
-// count    key = 2 * tile + species per particle; wave-aggregated counts
-// scan     one block: exclusive scan of the counts into segment offsets
-//          (clearing the counts for the next sort); reset every tile's box to
-//          its rectangle
+// count    key = 2 * tile + species per particle; wave-aggregated counts;
+//          the last block to finish scans the counts into segment offsets
+//          (clearing the counts for the next sort) and resets every tile's
+//          box to its rectangle
 // scatter  each particle to its segment of the other store
 // arrange  one block per segment: order the segment back into the current
 //          store by (rank within its cell, cell): first every cell's first
@@ -16,9 +16,9 @@
 //          addresses.  Ranks beyond `kcap` (dense cells) follow in cell order.
 //          The last arrange block to finish clears the request and counts
 //          the sort.  Between sorts the counts and cursors are zero, so a
-//          sort needs no clearing pass, and every kernel reads the request
-//          flag itself (only the particle kernel sets it, and it does not
-//          run during a sort).
+//          sort needs no clearing pass, and each of the three kernels reads
+//          the request flag itself (only the particle kernel sets it, and it
+//          does not run during a sort).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -59,6 +59,52 @@ __device__ int wave_add(int* ctr, int key, bool valid) {
 
 }  // namespace
 
+// Exclusive scan of the counts into segment offsets by one block (clearing
+// the counts for the next sort), and every tile's box reset to its
+// rectangle.  The counts were added with device-scope atomics; they are read
+// the same way.
+template <class Real>
+__device__ void scan_counts(const SortArgs<Real>& A, long long* part) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int chunk = (A.nkeys + nth - 1) / nth;
+  const int lo = tid * chunk;
+  const int hi = min(lo + chunk, A.nkeys);
+  long long s = 0;
+  for (int i = lo; i < hi; ++i) s += __hip_atomic_load(&A.counts[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < nth; off <<= 1) {
+    const long long v = (tid >= off) ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  long long base = part[tid] - s;  // exclusive
+  for (int i = lo; i < hi; ++i) {
+    const int c = __hip_atomic_load(&A.counts[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    A.seg[i] = (int)base;
+    base += c;
+    A.counts[i] = 0;
+  }
+  if (tid == nth - 1) A.seg[A.nkeys] = (int)part[nth - 1];
+  // every tile's particles now lie in its rectangle; its current bounds are
+  // rebuilt by the arrange pass
+  for (int i = tid; i < 4 * A.G; i += nth) A.jb[i] = 0.0f;
+  for (int g = tid; g < A.G; g += nth) {
+    const RunDev<Real>& R = A.runs[A.tile_run[g]];
+    const int lt = g - R.tile0;
+    int tc[3];
+    tc[0] = lt % R.ntile[0];
+    tc[1] = (lt / R.ntile[0]) % R.ntile[1];
+    tc[2] = lt / (R.ntile[0] * R.ntile[1]);
+    for (int d = 0; d < 3; ++d) {
+      const int org = tc[d] * A.tile[d];
+      A.bbox[g * 6 + 2 * d] = 0;
+      A.bbox[g * 6 + 2 * d + 1] = min(A.tile[d], R.n[d] - org) - 1;
+    }
+  }
+}
+
 template <class P, int DIM>
 __global__ void sort_count(SortArgs<typename P::Real> A) {
   using Real = typename P::Real;
@@ -97,49 +143,19 @@ __global__ void sort_count(SortArgs<typename P::Real> A) {
     }
     wave_add(A.counts, key, valid);
   }
-}
-
-template <class Real>
-__global__ void sort_scan(SortArgs<Real> A) {
-  if (!A.st->sort_request) return;
-  __shared__ long long part[1024];
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int chunk = (A.nkeys + nth - 1) / nth;
-  const int lo = tid * chunk;
-  const int hi = min(lo + chunk, A.nkeys);
-  long long s = 0;
-  for (int i = lo; i < hi; ++i) s += A.counts[i];
-  part[tid] = s;
+  // the last block to finish turns the counts into segment offsets
+  __shared__ long long part[256];
+  __shared__ int last;
   __syncthreads();
-  for (int off = 1; off < nth; off <<= 1) {
-    const long long v = (tid >= off) ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&A.st->count_done, 1u) == gridDim.x - 1;
   }
-  long long base = part[tid] - s;  // exclusive
-  for (int i = lo; i < hi; ++i) {
-    A.seg[i] = (int)base;
-    base += A.counts[i];
-    A.counts[i] = 0;
-  }
-  if (tid == nth - 1) A.seg[A.nkeys] = (int)part[nth - 1];
-  // every tile's particles now lie in its rectangle; its current bounds are
-  // rebuilt by the arrange pass
-  for (int i = tid; i < 4 * A.G; i += nth) A.jb[i] = 0.0f;
-  for (int g = tid; g < A.G; g += nth) {
-    const RunDev<Real>& R = A.runs[A.tile_run[g]];
-    const int lt = g - R.tile0;
-    int tc[3];
-    tc[0] = lt % R.ntile[0];
-    tc[1] = (lt / R.ntile[0]) % R.ntile[1];
-    tc[2] = lt / (R.ntile[0] * R.ntile[1]);
-    for (int d = 0; d < 3; ++d) {
-      const int org = tc[d] * A.tile[d];
-      A.bbox[g * 6 + 2 * d] = 0;
-      A.bbox[g * 6 + 2 * d + 1] = min(A.tile[d], R.n[d] - org) - 1;
-    }
-  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  scan_counts(A, part);
+  if (threadIdx.x == 0) A.st->count_done = 0;
 }
 
 template <class P, int DIM>
@@ -324,7 +340,6 @@ __global__ void __launch_bounds__(kArrangeBlock) sort_arrange(SortArgs<typename 
 
 template <class P>
 hipError_t launch_sort(const SortArgs<typename P::Real>& a, int ndim, hipStream_t s) {
-  using Real = typename P::Real;
   const long long blocks = (a.np_total + 255) / 256;
   // grid-stride kernels: enough groups to fill the chip when a sort runs,
   // few enough that the launches between sorts (all exit at once) are cheap
@@ -333,7 +348,6 @@ hipError_t launch_sort(const SortArgs<typename P::Real>& a, int ndim, hipStream_
     hipLaunchKernelGGL((sort_count<P, 2>), dim3(grid), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((sort_count<P, 3>), dim3(grid), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(sort_scan<Real>, dim3(1), dim3(1024), 0, s, a);
   if (ndim == 2)
     hipLaunchKernelGGL((sort_scatter<P, 2>), dim3(grid), dim3(256), 0, s, a);
   else
