@@ -14,7 +14,7 @@ the oracle computes one by one:
 Tolerances are those of the one-step tests (FP64 1e-12; FP32 2e-6, J 1e-5;
 transverse J from helpers.current_tol, which scales with the transverse step).  Workloads:
   2D 1024x512, l=3, a=0.45, 16.8M particles (FP32 and FP64);
-  3D 256x128x128, l=2, a=0.5, 67.1M particles (FP32);
+  3D 256x128x128, l=2, a=0.5, 67.1M particles (FP32 and FP64);
   64 batched 2D runs, l=2, a = 0.1 .. 0.7 (FP32);
   2D 4096x2048, l=3, a=0.3, 268M particles (FP32 and FP64).
 """
@@ -150,8 +150,9 @@ def test_fullsize_2d_1024x512_cubic(orc, precision):
     _run(orc, inputs.config(2), precision, nsample=20000, nbox=6)
 
 
-def test_fullsize_3d_256x128x128(orc):
-    _run(orc, inputs.config(3), wt.PIC_MIXED32, nsample=4000, nbox=3)
+@pytest.mark.parametrize("precision", [wt.PIC_MIXED32, wt.PIC_FP64], ids=["fp32", "fp64"])
+def test_fullsize_3d_256x128x128(orc, precision):
+    _run(orc, inputs.config(3), precision, nsample=4000, nbox=3)
 
 
 def test_fullsize_batched_courant_sweep(orc):

@@ -48,12 +48,14 @@ def _oracle_current(orc, spec, sp, E, B):
     return out
 
 
-def _one_step(orc, spec, precision, seed=7, amp=0.05):
+def _one_step(orc, spec, precision, seed=7, amp=0.05, tile=None):
     fp32 = precision == wt.PIC_MIXED32
     sp, E, B = H.random_state(spec, seed, amp, fp32=fp32)
     (g, ref), (ge, _), (gp, _) = _oracle_current(orc, spec, sp, E, B)
     sim = wt.Sim([spec], precision)
     try:
+        if tile is not None:
+            wt.pic_set_tiling(sim.ctx, tile, 0, 0)
         sim.set_species(0, sp)
         sim.set_fields(0, E, B)
         sim.gpd()
@@ -111,6 +113,31 @@ def test_one_step_fp32(orc, spec):
     assert eu <= 2e-6
     for k in range(3):
         assert ej[k] <= H.current_tol(spec, k, True)
+
+
+TILINGS = [
+    # (spec, precision, tile): the other precision's 2D default, tiles whose
+    # width is odd (plain cell order in FP64) or not a power of two, and 3D
+    # tiles whose windows need more than 64 KB of LDS
+    (RunSpec(2, (70, 52), 3, 0.45, 50.0, 0.01, 3, 31), wt.PIC_MIXED32, (16, 16, 1)),
+    (RunSpec(2, (70, 52), 3, 0.45, 50.0, 0.01, 3, 32), wt.PIC_FP64, (32, 16, 1)),
+    (RunSpec(2, (50, 40), 2, 0.6, 20.0, 0.05, 3, 33, colocated=False), wt.PIC_FP64, (9, 8, 1)),
+    (RunSpec(2, (50, 40), 2, 0.6, 20.0, 0.05, 3, 34, colocated=False), wt.PIC_MIXED32, (12, 8, 1)),
+    (RunSpec(3, (24, 20, 16), 2, 0.5, 50.0, 0.01, 2, 35), wt.PIC_MIXED32, (8, 8, 4)),
+    (RunSpec(3, (24, 20, 16), 2, 0.5, 50.0, 0.01, 2, 36), wt.PIC_FP64, (8, 4, 4)),
+]
+
+
+@pytest.mark.parametrize("spec,precision,tile", TILINGS,
+                         ids=["%dd-%s-%s" % (c.ndim, "fp32" if p == wt.PIC_MIXED32 else "fp64",
+                                             "x".join(map(str, t[:c.ndim]))) for c, p, t in TILINGS])
+def test_one_step_explicit_tiling(orc, spec, precision, tile):
+    fp32 = precision == wt.PIC_MIXED32
+    ex, eu, ej = _one_step(orc, spec, precision, tile=tile)
+    assert ex <= (2e-6 if fp32 else 1e-12)
+    assert eu <= (2e-6 if fp32 else 1e-12)
+    for k in range(3):
+        assert ej[k] <= H.current_tol(spec, k, fp32)
 
 
 @pytest.mark.parametrize("ndim,solver,aniso", [(2, 0, False), (2, 1, False), (3, 0, False), (3, 1, False),
