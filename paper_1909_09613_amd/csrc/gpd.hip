@@ -865,8 +865,10 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (!kFix) {
       deposit([&](int c, int i, Real v) { lds_add<Acc>(Jl + c * jcap + i, Acc(v)); }, jx, jy, jz, Real(0));
     } else {
-      // a particle whose step (or |v3|) exceeds the tile's bound deposits
-      // into the coarse windows, so that no fine node sum can overflow
+      // a component whose step (or |v3|) exceeds the tile's bound deposits
+      // into the coarse windows, so that no fine node sum can overflow; the
+      // particle's other components stay in the fine windows (a kick along
+      // one axis leaves the others' precision alone)
       const Real m0 = fabs(dd[0]), m1 = fabs(dd[1]), m2 = (DIM == 2) ? fabs(vv[2]) : fabs(dd[2]);
       mnew[0] = fmax(mnew[0], m0);
       mnew[1] = fmax(mnew[1], m1);
@@ -875,8 +877,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         deposit([&](int c, int i, Real v) { lds_addq(Qf + c * jcap + i, v); },
                 jx * qinv[0], jy * qinv[1], jz * qinv[2], half);
       } else {
-        deposit([&](int c, int i, Real v) { lds_addq(Qc + c * jcap + i, v); },
-                jx * qcinv[0], jy * qcinv[1], jz * qcinv[2], half);
+        const bool f0 = m0 <= thr[0], f1 = m1 <= thr[1], f2 = m2 <= thr[2];
+        int* const W0 = f0 ? Qf : Qc;
+        int* const W1 = (f1 ? Qf : Qc) + jcap;
+        int* const W2 = (f2 ? Qf : Qc) + 2 * jcap;
+        deposit([&](int c, int i, Real v) { lds_addq((c == 0 ? W0 : (c == 1 ? W1 : W2)) + i, v); },
+                jx * (f0 ? qinv[0] : qcinv[0]), jy * (f1 ? qinv[1] : qcinv[1]), jz * (f2 ? qinv[2] : qcinv[2]),
+                half);
       }
     }
 

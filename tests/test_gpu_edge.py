@@ -8,7 +8,9 @@ state against the FP64 oracle, with the one-step tolerances:
   * positions on cell faces and just below the periodic end, particles at
     rest, and offsets that round up to the next cell in FP32 (carried into
     the cell index, as the oracle's quantisation does);
-  * every particle of a species at one point.
+  * every particle of a species at one point;
+  * (mixed precision) particles kicked far beyond the tile's bound of the
+    previous step, which take the coarse fixed-point windows.
 """
 import numpy as np
 import pytest
@@ -134,3 +136,65 @@ def test_all_particles_at_one_point(orc, precision):
     xs = [np.array([[7.3, 4.6, 0.0]] * spec.ncell), np.array([[7.3, 4.6, 0.0]] * spec.ncell)]
     # every particle of a species at one point: the densest possible cell
     _run(orc, spec, _species(spec, xs), precision)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_fixed_point_coarse_path(orc, ndim):
+    """A strong transverse field in a band of cells kicks the particles there
+    to transverse steps far above twice the largest step the sort recorded
+    for their tiles, so their current goes through the coarse windows; the
+    step still matches the oracle to the one-step tolerances."""
+    if ndim == 2:
+        spec = RunSpec(2, (48, 32), 3, 0.45, 50.0, 0.01, 4, 505)
+    else:
+        spec = RunSpec(3, (24, 16, 12), 2, 0.4, 50.0, 0.01, 2, 506)
+    rng = np.random.default_rng(11)
+    sp = inputs.make_species(spec)
+    for s in sp:
+        s["x"], s["u"] = inputs.quantize_fp32(s["x"], s["u"])
+    E = inputs.random_fields(rng, spec.ncell, 0.01).astype(np.float32).astype(np.float64)
+    B = inputs.random_fields(rng, spec.ncell, 0.01).astype(np.float32).astype(np.float64)
+    ix = np.arange(spec.ncell) % spec.n[0]
+    band = (ix >= 10) & (ix < 18)
+    E[1, band] = 2.0                                   # transverse kick
+    # the largest transverse step any loaded particle takes (bounds the tiles')
+    a = spec.courant
+    stored = max(float(np.max(np.abs(a * s["u"][:, 1] / np.sqrt(1.0 + np.sum(s["u"] ** 2, axis=1)))))
+                 for s in sp)
+    grids = []
+    for which in (None, 0, 1):
+        gg = H.oracle_grid(orc, spec)
+        gg.E[:] = E
+        gg.B[:] = B
+        gg.zero_J()
+        r = H.copy_species(sp)
+        for k, s in enumerate(r):
+            if which is None or which == k:
+                gg.push_species(s["x"], s["u"], s["qm"], s["Q"])
+        grids.append((gg, r))
+    (g, ref), (ge, _), (gp, _) = grids
+    # the kicked particles step far beyond twice that bound
+    kicked = 0
+    for s0, s1 in zip(sp, ref):
+        dy = np.abs(H.min_image(s1["x"][:, 1] - s0["x"][:, 1], spec.n[1]))
+        kicked += int(np.sum(dy > 4 * stored))
+    assert kicked > 50
+    sim = wt.Sim([spec], wt.PIC_MIXED32)
+    try:
+        sim.set_species(0, sp)
+        sim.set_fields(0, E, B)
+        sim.gpd()
+        got = [sim.particles(0, k) for k in range(2)]
+        _, _, J = sim.fields(0)
+        d = sim.diagnostics(0)
+        assert d.n_nonfinite == 0 and d.n_out_of_range == 0
+    finally:
+        sim.close()
+    ex, eu = H.particle_errors(spec, ref, got)
+    scale = np.max(np.abs(ge.J) + np.abs(gp.J), axis=1)
+    ej = [float(np.max(np.abs(J[k] - g.J[k])) / scale[k]) for k in range(3)]
+    print("coarse path %dD: kicked %d dx=%.2e du=%.2e dJ/scale=%s" % (
+        ndim, kicked, ex, eu, ["%.2e" % v for v in ej]), flush=True)
+    assert ex <= 2e-6 and eu <= 2e-6
+    for k in range(3):
+        assert ej[k] <= H.current_tol(spec, k, True)
