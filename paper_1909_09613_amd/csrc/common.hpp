@@ -123,6 +123,8 @@ struct GpdArgs {
   int guard[3];          // bbox extent above which a re-sort is requested
   int max_groups;        // workgroups launched (persistent, tile queue)
   int skip;              // some run uses the partially skipped calculation
+  int* coarse;           // 3D mixed precision: per-group coarse current windows (zero between tiles)
+  int coarse_cap;        // ints per group in coarse
 };
 
 // Position of a (possibly negative or >= n) lattice index on a periodic axis.

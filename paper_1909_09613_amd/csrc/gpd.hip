@@ -89,6 +89,12 @@ __device__ __forceinline__ void lds_addq(int* p, float v) {
 __device__ __forceinline__ void lds_addq(int* p, double v) {
   atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)(int)floor(v));
 }
+// The same into a workgroup's private window in global memory.
+__device__ __forceinline__ void glob_addq(int* p, float v) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)r);
+}
 
 // Keeps a tile-constant integer in a vector register.  The particle loop
 // uses about twenty of them next to the run's tables; left to scalar
@@ -288,6 +294,10 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // particles than (l+3)^3 times its densest cell, so its bound is the tile's
   // particle count, and the LDS the counts would take buys 3D tiles room
   constexpr bool kCnt = kFix && DIM == 2;
+  // 3D keeps its coarse windows in a private region of global memory (only
+  // the rare components above their bound touch them), so that its LDS
+  // leaves room for three groups per CU
+  constexpr bool kGlobCoarse = kFix && DIM == 3;
   Real qinv[3] = {Real(0), Real(0), Real(0)}, thr[3] = {Real(0), Real(0), Real(0)};
   Real qcinv[3] = {Real(0), Real(0), Real(0)};
   double qd[3] = {0.0, 0.0, 0.0}, qcd[3] = {0.0, 0.0, 0.0};
@@ -333,8 +343,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // fixed-point path: 3 fine and 3 coarse int windows, then (2D) the
   // particle count per cell
   int* Qf = reinterpret_cast<int*>(Jl);
-  int* Qc = Qf + 3 * jcap;
-  int* Cw = Qc + 3 * jcap;
+  int* Qc = kGlobCoarse ? A.coarse + (long long)blockIdx.x * A.coarse_cap : Qf + 3 * jcap;
+  int* Cw = Qf + 6 * jcap;
 
   // ---- stage E, B on the window; clear the current tile ------------------
   const int nfs = (smode == 1) ? 0 : fs[0] * fs[1] * fs[2];
@@ -364,12 +374,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     }
   }
   if (kFix) {
-    for (int i = tid; i < (kCnt ? 7 : 6) * jcap; i += nth) Qf[i] = 0;
+    for (int i = tid; i < (kCnt ? 7 : (kGlobCoarse ? 3 : 6)) * jcap; i += nth) Qf[i] = 0;
   } else {
     for (int i = tid; i < 3 * jcap; i += nth) Jl[i] = Acc(0);
   }
   if (tid < 6) sred[tid] = (tid & 1) ? INT_MIN : INT_MAX;
-  if (tid >= 6 && tid < 12) sred[tid] = 0;
+  if (tid >= 6 && tid < 13) sred[tid] = 0;
   __syncthreads();
 
   const PBuf<Real> B = A.buf[A.st->parity];
@@ -878,12 +888,25 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
                 jx * qinv[0], jy * qinv[1], jz * qinv[2], half);
       } else {
         const bool f0 = m0 <= thr[0], f1 = m1 <= thr[1], f2 = m2 <= thr[2];
-        int* const W0 = f0 ? Qf : Qc;
-        int* const W1 = (f1 ? Qf : Qc) + jcap;
-        int* const W2 = (f2 ? Qf : Qc) + 2 * jcap;
-        deposit([&](int c, int i, Real v) { lds_addq((c == 0 ? W0 : (c == 1 ? W1 : W2)) + i, v); },
-                jx * (f0 ? qinv[0] : qcinv[0]), jy * (f1 ? qinv[1] : qcinv[1]), jz * (f2 ? qinv[2] : qcinv[2]),
-                half);
+        if constexpr (kGlobCoarse) {
+          sred[12] = 1;  // the flush reads the global coarse window
+          deposit(
+              [&](int c, int i, Real v) {
+                if (c == 0 ? f0 : (c == 1 ? f1 : f2))
+                  lds_addq(Qf + c * jcap + i, v);
+                else
+                  glob_addq(Qc + c * jcap + i, v);
+              },
+              jx * (f0 ? qinv[0] : qcinv[0]), jy * (f1 ? qinv[1] : qcinv[1]), jz * (f2 ? qinv[2] : qcinv[2]),
+              half);
+        } else {
+          int* const W0 = f0 ? Qf : Qc;
+          int* const W1 = (f1 ? Qf : Qc) + jcap;
+          int* const W2 = (f2 ? Qf : Qc) + 2 * jcap;
+          deposit([&](int c, int i, Real v) { lds_addq((c == 0 ? W0 : (c == 1 ? W1 : W2)) + i, v); },
+                  jx * (f0 ? qinv[0] : qcinv[0]), jy * (f1 ? qinv[1] : qcinv[1]),
+                  jz * (f2 ? qinv[2] : qcinv[2]), half);
+        }
       }
     }
 
@@ -961,6 +984,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 
   // ---- flush the current tile ------------------------------------------------
   double* Jg = A.J + R.cell0;
+  [[maybe_unused]] const bool coarse_used = kGlobCoarse && sred[12] != 0;
   const int njs = (smode == 1) ? 0 : jsz[0] * jsz[1] * jsz[2];
   for (int i = tid; i < njs; i += nth) {
     const int w0 = i % jsz[0];
@@ -974,11 +998,24 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     const int li = w0 + jwx * (w1 + jwy * w2);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double v = kFix ? (double)Qf[c * jcap + li] * qd[c] + (double)Qc[c * jcap + li] * qcd[c]
-                            : (double)Jl[c * jcap + li];
+      double v;
+      if constexpr (kGlobCoarse) {
+        v = (double)Qf[c * jcap + li] * qd[c];
+        if (coarse_used) {
+          // the coarse sums were added at the L2; read them there and leave
+          // the window zero for the group's next tile
+          int* q = Qc + c * jcap + li;
+          v += (double)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * qcd[c];
+          __hip_atomic_store(q, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      } else {
+        v = kFix ? (double)Qf[c * jcap + li] * qd[c] + (double)Qc[c * jcap + li] * qcd[c]
+                 : (double)Jl[c * jcap + li];
+      }
       if (v != 0.0) unsafeAtomicAdd(Jg + c * NT + gi, v);
     }
   }
+  if (kGlobCoarse && coarse_used) __threadfence();  // the clears land before the next tile's adds
 
   if (kCnt) __syncthreads();
   if (tid == 0) {
@@ -1026,7 +1063,7 @@ __attribute__((amdgpu_waves_per_eu(SKIP ? (DIM == 2 ? 4 : 3) : 1)))
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
                const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
-  __shared__ int sred[12];
+  __shared__ int sred[13];
   __shared__ int next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(&A.st->tile_queue, 1);

@@ -21,6 +21,8 @@ thread_local std::string g_err = "no error";
 // smallest tile edge; bounds the scratch layout
 int min_tile(int ndim) { return ndim == 2 ? 4 : 2; }
 constexpr int kMaxLds = 160 * 1024;     // LDS of a gfx950 CU: the most one workgroup can take
+constexpr int kMaxGroups = 2048;        // persistent particle-kernel groups (8 per CU of 256)
+constexpr int kCoarseCap = 3 * (kMaxLds / 12);  // ints of one group's coarse windows (3D mixed)
 // budget of the default tile choice: half a CU's LDS, so that two groups
 // share a CU (measured in 3D: 8x4x4 FP32 tiles at 69 KB and 4x4x4 FP64 tiles
 // at 67 KB beat the smaller tiles that fit 64 KB by 8% and 15%)
@@ -56,7 +58,8 @@ struct Layout {
   // fields / current: component-major
   // scratch
   size_t s_state, s_runs, s_tile_run, s_counts, s_cursor, s_seg, s_bbox, s_jb, s_keys, s_blk_run, s_blk_first, s_acc,
-      s_part, s_rho;
+      s_part, s_rho, s_coarse;
+  size_t coarse_bytes;
   long long gmax;
   long long nblocks;
 };
@@ -188,6 +191,10 @@ Layout make_layout(const pic_run_desc* runs, int n_runs) {
   off += align_up(8 * 16 * (size_t)kDiagBlocks);
   L.s_rho = off;
   off += align_up(8 * maxc);
+  // 3D mixed precision: each particle-kernel group's coarse current windows
+  L.s_coarse = off;
+  L.coarse_bytes = (ndim == 3 && !f64) ? (size_t)4 * kCoarseCap * kMaxGroups : 0;
+  off += align_up(L.coarse_bytes);
   L.bytes[3] = off;
   return L;
 }
@@ -409,9 +416,12 @@ pic_status apply_tiling(pic_ctx* c) {
   const size_t fcap = (size_t)c->fw[0] * c->fw[1] * c->fw[2];
   const size_t jcap = (size_t)c->jw[0] * c->jw[1] * c->jw[2];
   const size_t rs = sizeof(Real);
-  // FP32: fine and coarse fixed-point current windows and, in 2D, a cell
-  // count (7 or 6 ints per node); FP64: FP64 current windows
-  c->lds = 6 * rs * fcap + (c->f64() ? 3 * sizeof(double) : (nd == 2 ? 7 : 6) * sizeof(int)) * jcap;
+  // FP32: fine and coarse fixed-point current windows and a cell count in
+  // 2D (7 ints per node), the fine windows in 3D (3 ints; its coarse ones
+  // are in global memory); FP64: FP64 current windows
+  c->lds = 6 * rs * fcap + (c->f64() ? 3 * sizeof(double) : (nd == 2 ? 7 : 3) * sizeof(int)) * jcap;
+  if (nd == 3 && !c->f64() && 3 * jcap > (size_t)kCoarseCap)
+    return c->fail(PIC_ERR_ARG, "tile too large for the coarse current windows");
   if (c->lds > (size_t)c->lds_budget) return c->fail(PIC_ERR_ARG, "tile and margin need more LDS than the workgroup budget");
   // device tables
   c->tile_run_host.assign(G, 0);
@@ -443,8 +453,11 @@ pic_status upload_static(pic_ctx* c) {
   if (e == hipSuccess) e = hipMemsetAsync(c->J, 0, c->lay.bytes[2], c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->P, 0, c->lay.bytes[0], c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->S + c->lay.s_state, 0, sizeof(DevState), c->stream);
-  // the sort keeps its counts and cursors zero between sorts
+  // the sort keeps its counts and cursors zero between sorts, the particle
+  // kernel its global coarse windows
   if (e == hipSuccess) e = hipMemsetAsync(c->S + c->lay.s_counts, 0, c->lay.s_seg - c->lay.s_counts, c->stream);
+  if (e == hipSuccess && c->lay.coarse_bytes)
+    e = hipMemsetAsync(c->S + c->lay.s_coarse, 0, c->lay.coarse_bytes, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return c->hip(e, "init upload");
 }
@@ -467,6 +480,8 @@ GpdArgs<Real> gpd_args(pic_ctx* c) {
   a.max_groups = c->max_groups;
   a.skip = 0;
   for (const RunHost& H : c->runs) a.skip |= H.skip_on ? 1 : 0;
+  a.coarse = reinterpret_cast<int*>(c->S + c->lay.s_coarse);
+  a.coarse_cap = kCoarseCap;
   for (int k = 0; k < 3; ++k) {
     a.tile[k] = c->tile[k];
     a.fw[k] = c->fw[k];
@@ -871,15 +886,20 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
         hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 0)
       c->lds_budget = std::min<size_t>((size_t)lim, (size_t)kMaxLds);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      c->max_groups = 8 * cus;  // more than fit at once; the extra ones find the queue empty
+      c->max_groups = std::min(8 * cus, kMaxGroups);  // more than fit at once; the extra ones find the queue empty
   }
   // measured in 2D (1024x512 cubic; 64 batched runs; 4096x2048): FP32 is
   // fastest with 32 x 16 tiles (7%, 13% and 2% ahead of 16 x 16; 32 x 32
   // and 64 x 16 need more than half the LDS), FP64 with 16 x 16
   static const int cand2s[][3] = {{32, 16, 1}, {16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}};
   static const int cand2d[][3] = {{16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}, {4, 4, 1}};
-  static const int cand3[][3] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}};
+  // 3D: FP64 takes the largest tile within half a CU's LDS (4x4x4); mixed
+  // precision keeps only its fine current windows in LDS, and 8x4x4 (47 KB,
+  // three groups per CU) measured 14% ahead of 8x8x4 (66 KB, two)
+  static const int cand3s[][3] = {{8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}, {2, 2, 2}};
+  static const int cand3d[][3] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}};
   const int (*cand2)[3] = c->f64() ? cand2d : cand2s;
+  const int (*cand3)[3] = c->f64() ? cand3d : cand3s;
   const int ncand = 6;
   c->margin = (c->ndim == 2) ? 3 : 2;
   c->sort_every = (c->ndim == 2) ? 2 : 1;
