@@ -1,5 +1,5 @@
 """The benchmark's command-line contract that holds without a GPU: more than
-one GPU is refused with a message and a nonzero status (this build measures
+one GPU is refused with a message and a nonzero status (the benchmark measures
 one GPU), and the workload and option names parse."""
 import os
 import subprocess
