@@ -1260,6 +1260,36 @@ hipError_t launch_rho_tiles(const GpdArgs<typename P::Real>& a, int run, int nti
   return hipErrorInvalidValue;
 }
 
+template <class P, int L, int DIM>
+static int occupancy_one(size_t lds, bool skip) {
+  const void* k = skip ? reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, true>)
+                       : reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, false>);
+  if (lds > 64 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, gpd_block<DIM>(), lds);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+template <class P>
+int gpd_groups_per_cu(int order, int ndim, size_t lds, bool skip) {
+  if (ndim == 2) {
+    switch (order) {
+      case 1: return occupancy_one<P, 1, 2>(lds, skip);
+      case 2: return occupancy_one<P, 2, 2>(lds, skip);
+      case 3: return occupancy_one<P, 3, 2>(lds, skip);
+      case 4: return occupancy_one<P, 4, 2>(lds, skip);
+    }
+  } else {
+    switch (order) {
+      case 1: return occupancy_one<P, 1, 3>(lds, skip);
+      case 2: return occupancy_one<P, 2, 3>(lds, skip);
+      case 3: return occupancy_one<P, 3, 3>(lds, skip);
+      case 4: return occupancy_one<P, 4, 3>(lds, skip);
+    }
+  }
+  return 1;
+}
+
 template <class P>
 hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, size_t lds, hipStream_t s) {
   if (ndim == 2) {
@@ -1283,10 +1313,12 @@ hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, s
 // Each precision policy can be built as a translation unit of its own
 // (WTPIC_GPD_POLICY = 32 or 64), so that the two compile in parallel.
 #if !defined(WTPIC_GPD_POLICY) || WTPIC_GPD_POLICY == 32
+template int gpd_groups_per_cu<F32>(int, int, size_t, bool);
 template hipError_t launch_gpd<F32>(const GpdArgs<float>&, int, int, size_t, hipStream_t);
 template hipError_t launch_rho_tiles<F32>(const GpdArgs<float>&, int, int, double*, int, int, size_t, hipStream_t);
 #endif
 #if !defined(WTPIC_GPD_POLICY) || WTPIC_GPD_POLICY == 64
+template int gpd_groups_per_cu<F64>(int, int, size_t, bool);
 template hipError_t launch_gpd<F64>(const GpdArgs<double>&, int, int, size_t, hipStream_t);
 template hipError_t launch_rho_tiles<F64>(const GpdArgs<double>&, int, int, double*, int, int, size_t, hipStream_t);
 #endif

@@ -69,6 +69,11 @@ constexpr int kDiagBlocks = 2048;
 template <class P>
 hipError_t launch_gpd(const GpdArgs<typename P::Real>& a, int order, int ndim, size_t lds, hipStream_t s);
 
+// Particle-kernel groups one CU holds at once with lds bytes of dynamic LDS
+// (plain or skip variant), at least 1.
+template <class P>
+int gpd_groups_per_cu(int order, int ndim, size_t lds, bool skip);
+
 // Charge density of one run from the tile segments (diagnostics); lds bytes
 // must hold 8 * (current window nodes).
 template <class P>
