@@ -185,13 +185,14 @@ __global__ void sort_scatter(SortArgs<typename P::Real> A) {
 }
 
 // Index of a particle's cell in the order the arrange pass lays cells out.
-// FP64 with an even tile width: first the cells of even x, then those of odd
-// x (each in x-then-y-then-z order), so that the lanes of a wave sit two
-// cells apart along x and particles that drift at slightly different times
-// still fall in different cells (same-address LDS atomics serialise; FP64
-// atomics are the FP64 kernel's bound).  Otherwise plain x-fastest order,
-// which measured 1-3% faster for the fixed-point current of the mixed
-// precision path and 5% slower in FP64.
+// With an even tile width, in FP64 and for 2D tiles narrower than 32 cells:
+// first the cells of even x, then those of odd x (each in x-then-y-then-z
+// order), so that the lanes of a wave sit two cells apart along x and
+// particles that drift at slightly different times still fall in different
+// cells (same-address LDS atomics serialise).  Otherwise plain x-fastest
+// order.  Measured in 2D: FP64 16x16 5% faster with the split; mixed
+// precision 32x16 and 64x8 1-6% faster without it, 16x16 and 16x32 8-10%
+// faster with it; 3D mixed precision 3% faster without it.
 template <class P, int DIM>
 __device__ __forceinline__ int cell_in_tile(const PBuf<typename P::Real>& S, long long q, const int org[3],
                                             const int tile[3]) {
@@ -203,7 +204,7 @@ __device__ __forceinline__ int cell_in_tile(const PBuf<typename P::Real>& S, lon
   }
   int m[3] = {0, 0, 0};
   for (int d = 0; d < DIM; ++d) m[d] = min(max(c[d] - org[d], 0), tile[d] - 1);
-  if (P::kAbs && (tile[0] & 1) == 0) {
+  if ((P::kAbs || (DIM == 2 && tile[0] < 32)) && (tile[0] & 1) == 0) {
     const int h = tile[0] >> 1;
     const int rest = m[1] + tile[1] * m[2];
     const int nrest = tile[1] * (DIM == 3 ? tile[2] : 1);
