@@ -22,7 +22,7 @@ its algorithmic bytes per
 launch (particle state read and written once, E and B read and J written once
 per cell) over that time.  `traffic` is the HBM traffic per launch from the
 rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded under profiles/ for the
-current kernel source, else null.  `cpu_baseline` is the FP64 CPU oracle
+current kernel source and the default tiling, else null.  `cpu_baseline` is the FP64 CPU oracle
 timed on a bounded sample of the same workload on one host core.
 """
 import argparse
@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--tile", default=None, help="tile shape, e.g. 32x16")
     ap.add_argument("--margin", type=int, default=0, help="staging margin in cells (0 = default)")
     ap.add_argument("--sort-every", type=int, default=0, help="sort check cadence in steps (0 = default)")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="time the library's candidate tilings over this many steps each and keep the "
+                         "fastest (0 = the default tiling)")
     ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5], help="workload")
     ap.add_argument("--skip-strip", type=float, default=0.0,
                     help="partially skipped calculation: initially perturbed strip of this width (cells, "
@@ -159,6 +162,10 @@ def main():
             mid = 0.5 * sr.n[0]
             sim.set_skip_region(r, (mid - 0.5 * args.skip_strip, 0.0, 0.0),
                                 (mid + 0.5 * args.skip_strip, float(sr.n[1]), float(sr.n3[2])), 0.0)
+    tuned = None
+    if args.autotune > 0:
+        tuned = sim.autotune(args.autotune)
+        print("autotune: %s" % (tuned,), file=sys.stderr, flush=True)
     np_total = sum(2 * sr.ncell * sr.ppc_s for sr in specs)
     ncell_total = sum(sr.ncell for sr in specs)
     print("setup %.1f s, %d particles" % (time.perf_counter() - t_setup, np_total), file=sys.stderr, flush=True)
@@ -249,7 +256,9 @@ def main():
     alg_bytes = np_total * particle_bytes(spec.ndim, prec_name) + ncell_total * cell_bytes(prec_name)
     achieved = alg_bytes / (gpd_ms / 1e3) / 1e9
     digest = source_digest()
-    traffic = load_traffic(prec_name, digest) if args.config == 2 else None
+    # the stored counters were taken with the default tiling on this workload
+    default_tiling = not (tuned or args.tile or args.margin or args.sort_every)
+    traffic = load_traffic(prec_name, digest) if args.config == 2 and default_tiling else None
 
     if not args.no_cpu:
         rng = np.random.default_rng(0)
@@ -295,6 +304,7 @@ def main():
             "diagnostics_call_ms": float(np.median(diag_ms)),
         },
         "cpu_baseline": cpu,
+        "autotune": tuned,
         "skip": None if args.skip_strip <= 0 else {
             "strip_cells": args.skip_strip,
             "t_end": t_end,

@@ -193,6 +193,25 @@ pic_status pic_set_skip_region(pic_ctx *ctx, int32_t run, const double *lo, cons
  * (160 KB), if margin <= sort_every, or if a tile has more than 4096 cells. */
 pic_status pic_set_tiling(pic_ctx *ctx, const int32_t tile[3], int32_t margin, int32_t sort_every);
 
+/* Autotuner of the tiling (the library's own: the paper has no tiling).  For
+ * each candidate of a fixed list for the context's dimension and precision
+ * (tile shape, staging margin, sort cadence; the first is the default
+ * tiling), skipping those whose windows exceed the LDS, it takes untimed steps
+ * (the candidate's first full sort and graph capture) and then times
+ * trial_steps full steps, rounded up to a whole graph, with HIP events around
+ * graph replays on the context stream; the fastest candidate is applied as
+ * pic_set_tiling would.  The trial steps are then undone: the current
+ * particle store, the fields, the current and the device counters are copied
+ * to pageable host memory before the trials (about the size of one particle
+ * store plus the grids) and back afterwards, so the next step starts from the
+ * state the call found.  chosen (host, 5 int32, may be NULL) receives tile[0],
+ * tile[1], tile[2], margin and sort_every; *best_ms (may be NULL) the chosen
+ * candidate's milliseconds per step.  Synchronises the stream.  PIC_ERR_ARG
+ * unless 1 <= trial_steps <= 4096; PIC_ERR_STATE after the first step or
+ * before the particles of every run and species are set; a trial's failure is
+ * returned after the state and the previous tiling are restored. */
+pic_status pic_autotune(pic_ctx *ctx, int32_t trial_steps, int32_t chosen[5], double *best_ms);
+
 /* Device timing of the gather-push-deposit kernel.  enable != 0 starts
  * recording a HIP event pair around every gather-push-deposit kernel launch
  * on the context stream (eager launches only; pic_step graphs are not

@@ -31,7 +31,7 @@ EXPORTED = [
     "pic_query_layout", "pic_init", "pic_set_particles", "pic_get_particles", "pic_set_fields",
     "pic_get_fields", "pic_gather_push_deposit", "pic_field_update", "pic_step", "pic_step_diag",
     "pic_diagnostics",
-    "pic_set_tiling", "pic_set_skip_region", "pic_kernel_timing", "pic_last_error", "pic_destroy", "pic_table_weights",
+    "pic_set_tiling", "pic_autotune", "pic_set_skip_region", "pic_kernel_timing", "pic_last_error", "pic_destroy", "pic_table_weights",
 ]
 
 
@@ -103,6 +103,7 @@ def lib():
             "pic_set_tiling": [vp, ctypes.POINTER(i32), i32, i32],
             "pic_set_skip_region": [vp, i32, dp, dp, ctypes.c_double],
             "pic_kernel_timing": [vp, i32, dp, ctypes.POINTER(i64)],
+            "pic_autotune": [vp, i32, ctypes.POINTER(i32), dp],
             "pic_destroy": [vp],
             "pic_table_weights": [i32, i32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32),
                                   ctypes.POINTER(i32), dp],
@@ -248,6 +249,15 @@ def pic_kernel_timing(ctx, enable):
     return ms.value, n.value
 
 
+def pic_autotune(ctx, trial_steps=16):
+    """Times the candidate tilings on the context's own workload, applies the
+    fastest and undoes the trial steps; returns the choice."""
+    ch = (ctypes.c_int32 * 5)()
+    ms = ctypes.c_double()
+    _check(lib().pic_autotune(ctx, trial_steps, ch, ctypes.byref(ms)), ctx)
+    return {"tile": tuple(ch[0:3]), "margin": ch[3], "sort_every": ch[4], "ms_per_step": ms.value}
+
+
 def pic_last_error(ctx=None):
     return lib().pic_last_error(ctx).decode(errors="replace")
 
@@ -315,6 +325,9 @@ class Sim:
 
     def step(self, n=1):
         pic_step(self.ctx, n)
+
+    def autotune(self, trial_steps=16):
+        return pic_autotune(self.ctx, trial_steps)
 
     def set_skip_region(self, run, lo=None, hi=None, t0=0.0):
         pic_set_skip_region(self.ctx, run, lo, hi, t0)

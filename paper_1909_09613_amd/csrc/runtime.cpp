@@ -1097,6 +1097,131 @@ pic_status pic_step_diag(pic_ctx* c, int32_t n_steps, int32_t diag_every, int32_
   return pic_step(c, n_steps % diag_every);
 }
 
+// Autotuner of the tiling.  Each candidate is timed over graph-replayed
+// steps of the context's own workload, after untimed steps that take its first
+// (full) sort and its graph capture.  The trial steps are undone afterwards
+// from a host copy of the current particle store, the fields, the current and
+// the device state, so the simulation resumes from where it was.
+pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, int32_t chosen[5], double* best_ms) {
+  if (!c) return PIC_ERR_ARG;
+  if (trial_steps < 1 || trial_steps > 4096) return c->fail(PIC_ERR_ARG, "trial_steps must be in 1..4096");
+  if (c->started) return c->fail(PIC_ERR_STATE, "autotune must run before the first step");
+  pic_status st = check_ready(c);
+  if (st != PIC_OK) return st;
+  // tile (cells), staging margin, sort cadence; the first is the default
+  struct Cand {
+    int t[3], margin, every;
+  };
+  static const Cand c2s[] = {{{32, 16, 1}, 3, 2}, {{16, 16, 1}, 3, 2}, {{16, 32, 1}, 3, 2}, {{64, 8, 1}, 3, 2},
+                             {{32, 8, 1}, 3, 2},  {{32, 16, 1}, 2, 1}, {{16, 16, 1}, 2, 1}};
+  static const Cand c2d[] = {{{16, 16, 1}, 3, 2}, {{16, 8, 1}, 3, 2}, {{32, 8, 1}, 3, 2},
+                             {{8, 16, 1}, 3, 2},  {{32, 16, 1}, 3, 2}, {{16, 16, 1}, 2, 1}};
+  static const Cand c3s[] = {{{8, 4, 4}, 2, 1}, {{8, 8, 2}, 2, 1}, {{4, 4, 4}, 2, 1},
+                             {{16, 4, 4}, 2, 1}, {{8, 8, 4}, 2, 1}, {{8, 4, 4}, 3, 2}};
+  static const Cand c3d[] = {{{4, 4, 4}, 2, 1}, {{8, 4, 4}, 2, 1}, {{4, 4, 2}, 2, 1}, {{8, 8, 2}, 2, 1},
+                             {{4, 4, 4}, 3, 2}};
+  const Cand* cand = c->ndim == 2 ? (c->f64() ? c2d : c2s) : (c->f64() ? c3d : c3s);
+  const int ncand = c->ndim == 2 ? (c->f64() ? 6 : 7) : (c->f64() ? 5 : 6);
+
+  // snapshot: the current particle store (the other one is the sort's
+  // destination and holds nothing yet), fields, current, device state
+  const int par = read_parity(c, &st);
+  if (st != PIC_OK) return st;
+  const size_t p_lo = c->lay.p_cell[par];
+  const size_t p_hi = par == 0 ? c->lay.p_cell[1] : c->lay.bytes[0];
+  std::vector<char> hp(p_hi - p_lo), hf(c->lay.bytes[1]), hj(c->lay.bytes[2]);
+  DevState ds{};
+  hipError_t e = host_copy(c, hp.data(), c->P + p_lo, hp.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = host_copy(c, hf.data(), c->F, hf.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = host_copy(c, hj.data(), c->J, hj.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = host_copy(c, &ds, c->state(), sizeof ds, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return c->hip(e, "autotune snapshot");
+  const Cand keep = {{c->tile[0], c->tile[1], c->tile[2]}, c->margin, c->sort_every};
+  const bool keep_timing = c->timing, keep_sorted = c->sorted_once;
+  const long long step0 = c->step;
+  c->timing = false;
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  double best = 0.0;
+  int bi = -1;
+  for (int i = 0; i < ncand && e == hipSuccess && st == PIC_OK; ++i) {
+    for (int k = 0; k < 3; ++k) c->tile[k] = k < c->ndim ? cand[i].t[k] : 1;
+    c->margin = cand[i].margin;
+    c->sort_every = cand[i].every;
+    if ((c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c)) != PIC_OK) continue;  // LDS too small
+    drop_graph(c);
+    // the sort kernels run only on a device-side request: the particles are
+    // still in the previous tiling's tile order
+    c->force_sort = true;
+    const int one = 1;
+    e = host_copy(c, &c->state()->sort_request, &one, sizeof one, hipMemcpyHostToDevice);
+    DevState d0{}, d1{};
+    if (e == hipSuccess) e = host_copy(c, &d0, c->state(), sizeof d0, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) break;
+    const int per_graph = c->sort_every * std::max(1, 8 / c->sort_every);
+    const int timed = (trial_steps + per_graph - 1) / per_graph * per_graph;
+    st = pic_step(c, 2 * per_graph);
+    if (st != PIC_OK) break;
+    e = hipEventRecord(e0, c->stream);
+    if (e == hipSuccess) st = pic_step(c, timed);
+    if (e == hipSuccess && st == PIC_OK) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess && st == PIC_OK) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && st == PIC_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && st == PIC_OK) e = host_copy(c, &d1, c->state(), sizeof d1, hipMemcpyDeviceToHost);
+    if (e != hipSuccess || st != PIC_OK) break;
+    // a tile whose particles outgrew its windows is left unprocessed (and
+    // counted): such a trial is not a measurement of the tiling
+    if (d1.n_out_of_range != d0.n_out_of_range || d1.n_nonfinite != d0.n_nonfinite) {
+      st = c->fail(PIC_ERR_NUMERIC, "autotune: a trial step left particles out of range or non-finite");
+      break;
+    }
+    if (bi < 0 || ms / timed < best) {
+      best = ms / timed;
+      bi = i;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  std::string trial_err;
+  if (e != hipSuccess)
+    trial_err = std::string("autotune trial: ") + hipGetErrorString(e);
+  else if (st != PIC_OK)
+    trial_err = c->err;
+
+  // the chosen tiling (the previous one if no candidate ran), then the state
+  const Cand& pick = (bi >= 0 && trial_err.empty()) ? cand[bi] : keep;
+  for (int k = 0; k < 3; ++k) c->tile[k] = k < c->ndim ? pick.t[k] : 1;
+  c->margin = pick.margin;
+  c->sort_every = pick.every;
+  pic_status rs = c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c);
+  drop_graph(c);
+  ds.sort_request = 1;  // the first step sorts into the chosen tiling
+  hipError_t re = host_copy(c, c->P + p_lo, hp.data(), hp.size(), hipMemcpyHostToDevice);
+  if (re == hipSuccess) re = host_copy(c, c->F, hf.data(), hf.size(), hipMemcpyHostToDevice);
+  if (re == hipSuccess) re = host_copy(c, c->J, hj.data(), hj.size(), hipMemcpyHostToDevice);
+  if (re == hipSuccess) re = host_copy(c, c->state(), &ds, sizeof ds, hipMemcpyHostToDevice);
+  if (re == hipSuccess) re = hipStreamSynchronize(c->stream);
+  c->step = step0;
+  c->started = false;
+  c->force_sort = true;
+  c->sorted_once = keep_sorted;
+  c->timing = keep_timing;
+  if (re != hipSuccess) return c->hip(re, "autotune restore");
+  if (rs != PIC_OK) return rs;
+  if (!trial_err.empty()) return c->fail(e != hipSuccess ? PIC_ERR_HIP : st, trial_err);
+  if (bi < 0) return c->fail(PIC_ERR_ARG, "no candidate tiling fits the LDS");
+  if (chosen) {
+    for (int k = 0; k < 3; ++k) chosen[k] = c->tile[k];
+    chosen[3] = c->margin;
+    chosen[4] = c->sort_every;
+  }
+  if (best_ms) *best_ms = best;
+  return PIC_OK;
+}
+
 pic_status pic_diagnostics(pic_ctx* c, int32_t run, pic_diag* out) {
   if (!c) return PIC_ERR_ARG;
   if (run < 0 || run >= c->nruns || !out) return c->fail(PIC_ERR_ARG, "bad run or NULL out");

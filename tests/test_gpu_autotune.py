@@ -1,0 +1,107 @@
+"""GPU tests of the tiling autotuner (pic_autotune): it picks a tiling from its
+candidate list, leaves the simulation state exactly as it found it (the trial
+steps are undone), and the steps taken afterwards with the chosen tiling match
+those of a context that keeps the default tiling (the tiling changes only the
+order in which current contributions are summed).
+"""
+import numpy as np
+import pytest
+
+import paper_1909_09613_amd as wt
+from paper_1909_09613_amd.inputs import RunSpec
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+# the candidate tile shapes of each (dimension, precision), first the default
+CANDS = {
+    (2, wt.PIC_MIXED32): {(32, 16, 1), (16, 16, 1), (16, 32, 1), (64, 8, 1), (32, 8, 1)},
+    (2, wt.PIC_FP64): {(16, 16, 1), (16, 8, 1), (32, 8, 1), (8, 16, 1), (32, 16, 1)},
+    (3, wt.PIC_MIXED32): {(8, 4, 4), (8, 8, 2), (4, 4, 4), (16, 4, 4), (8, 8, 4)},
+    (3, wt.PIC_FP64): {(4, 4, 4), (8, 4, 4), (4, 4, 2), (8, 8, 2)},
+}
+
+CASES = [
+    (RunSpec(2, (72, 40), 3, 0.45, 50.0, 0.01, 4, 71), wt.PIC_MIXED32),
+    (RunSpec(2, (72, 40), 3, 0.45, 50.0, 0.01, 4, 72), wt.PIC_FP64),
+    (RunSpec(3, (24, 12, 10), 2, 0.5, 50.0, 0.01, 2, 73), wt.PIC_MIXED32),
+    (RunSpec(3, (24, 12, 10), 2, 0.5, 50.0, 0.01, 2, 74), wt.PIC_FP64),
+]
+
+
+def _state(sim, spec):
+    parts = [sim.particles(0, s) for s in range(2)]
+    return parts, sim.fields(0)
+
+
+@pytest.mark.parametrize("spec,precision", CASES,
+                         ids=["%dd-%s" % (c.ndim, "fp64" if p == wt.PIC_FP64 else "mixed32") for c, p in CASES])
+def test_autotune_restores_state_and_steps_like_default(spec, precision):
+    fp32 = precision == wt.PIC_MIXED32
+    sp, E, B = H.random_state(spec, 5, amp=0.05, fp32=fp32)
+    a = wt.Sim([spec], precision)
+    b = wt.Sim([spec], precision)
+    try:
+        for sim in (a, b):
+            sim.set_species(0, sp)
+            sim.set_fields(0, E, B)
+        before = _state(a, spec)
+        r = a.autotune(8)
+        print("autotune %s: %s" % (spec.n, r), flush=True)
+        after = _state(a, spec)
+        assert r["tile"] in CANDS[(spec.ndim, precision)]
+        assert r["sort_every"] in (1, 2) and r["margin"] > r["sort_every"]
+        assert r["ms_per_step"] > 0.0
+        # the trial steps are undone bit for bit
+        for s in range(2):
+            assert np.array_equal(before[0][s][0], after[0][s][0])
+            assert np.array_equal(before[0][s][1], after[0][s][1])
+        for k in range(3):
+            assert np.array_equal(before[1][k], after[1][k])
+        # a second call is allowed before the first step, and also undone
+        r2 = a.autotune(8)
+        assert r2["tile"] in CANDS[(spec.ndim, precision)]
+        for s in range(2):
+            assert np.array_equal(before[0][s][0], a.particles(0, s)[0])
+        a.step(6)
+        b.step(6)
+        da, db = a.diagnostics(0), b.diagnostics(0)
+        xa = [a.particles(0, s) for s in range(2)]
+        xb = [b.particles(0, s) for s in range(2)]
+        Ea, Ba, _ = a.fields(0)
+        Eb, Bb, _ = b.fields(0)
+    finally:
+        a.close()
+        b.close()
+    ref = [{"x": x, "u": u} for x, u in xb]
+    ex, eu = H.particle_errors(spec, ref, xa)
+    print("autotuned vs default after 6 steps: dx=%.2e du=%.2e" % (ex, eu), flush=True)
+    assert da.n_nonfinite == 0 and da.n_out_of_range == 0
+    assert db.n_nonfinite == 0 and db.n_out_of_range == 0
+    # FP64: summation order only; mixed precision: the fixed-point quantum of
+    # the per-tile current differs between tilings
+    tol_x, tol_u, tol_f = (1e-12, 1e-10, 1e-10) if not fp32 else (1e-5, 1e-4, 1e-4)
+    assert ex <= tol_x and eu <= tol_u
+    scale = max(1e-30, float(np.max(np.abs(Eb))))
+    assert float(np.max(np.abs(Ea - Eb))) <= tol_f * max(scale, 0.05)
+    assert float(np.max(np.abs(Ba - Bb))) <= tol_f * max(scale, 0.05)
+
+
+def test_autotune_arguments_and_state():
+    spec = RunSpec(2, (40, 32), 2, 0.45, 50.0, 0.01, 2, 75)
+    sim = wt.Sim([spec], wt.PIC_FP64)
+    try:
+        with pytest.raises(wt.PicError) as ei:
+            sim.autotune(8)  # particles not set
+        assert ei.value.status == wt.PIC_ERR_STATE
+        sim.set_species(0, H.random_state(spec, 1)[0])
+        for bad in (0, -3, 5000):
+            with pytest.raises(wt.PicError) as ei:
+                sim.autotune(bad)
+            assert ei.value.status == wt.PIC_ERR_ARG
+        sim.step(1)
+        with pytest.raises(wt.PicError) as ei:
+            sim.autotune(8)
+        assert ei.value.status == wt.PIC_ERR_STATE
+    finally:
+        sim.close()
