@@ -200,7 +200,9 @@ pic_status pic_set_tiling(pic_ctx *ctx, const int32_t tile[3], int32_t margin, i
  * (the candidate's first full sort and graph capture) and then times
  * trial_steps full steps, rounded up to a whole graph, with HIP events around
  * graph replays on the context stream; the fastest candidate is applied as
- * pic_set_tiling would.  The trial steps are then undone: the current
+ * pic_set_tiling would, except that the default stays unless another is more
+ * than 2% faster.  A trial that leaves particles out of range or non-finite
+ * fails the call with PIC_ERR_NUMERIC.  The trial steps are then undone: the current
  * particle store, the fields, the current and the device counters are copied
  * to pageable host memory before the trials (about the size of one particle
  * store plus the grids) and back afterwards, so the next step starts from the

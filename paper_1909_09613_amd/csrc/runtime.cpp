@@ -28,6 +28,7 @@ constexpr int kCoarseCap = 3 * (kMaxLds / 12);  // ints of one group's coarse wi
 // share a CU (measured in 3D: 8x4x4 FP32 tiles at 69 KB and 4x4x4 FP64 tiles
 // at 67 KB beat the smaller tiles that fit 64 KB by 8% and 15%)
 constexpr int kDefaultLds = 80 * 1024;
+constexpr double kTuneMargin = 0.02;  // autotuner: relative gain needed to leave the default tiling
 constexpr int kMaxTileCells = 4096; // the sort orders a tile's cells in LDS
 constexpr size_t kAlign = 256;
 
@@ -1144,7 +1145,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, int32_t chosen[5], doub
   hipEvent_t e0 = nullptr, e1 = nullptr;
   e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  double best = 0.0;
+  double best = 0.0, ms_first = 0.0;
   int bi = -1;
   for (int i = 0; i < ncand && e == hipSuccess && st == PIC_OK; ++i) {
     for (int k = 0; k < 3; ++k) c->tile[k] = k < c->ndim ? cand[i].t[k] : 1;
@@ -1178,10 +1179,17 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, int32_t chosen[5], doub
       st = c->fail(PIC_ERR_NUMERIC, "autotune: a trial step left particles out of range or non-finite");
       break;
     }
+    if (i == 0) ms_first = ms / timed;
     if (bi < 0 || ms / timed < best) {
       best = ms / timed;
       bi = i;
     }
+  }
+  // the default (first) candidate stays unless another is faster by more
+  // than the spread of repeated timings
+  if (bi > 0 && ms_first > 0.0 && best > (1.0 - kTuneMargin) * ms_first) {
+    best = ms_first;
+    bi = 0;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
