@@ -1121,8 +1121,15 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, int32_t chosen[5], doub
                              {{16, 4, 4}, 2, 1}, {{8, 8, 4}, 2, 1}, {{8, 4, 4}, 3, 2}};
   static const Cand c3d[] = {{{4, 4, 4}, 2, 1}, {{8, 4, 4}, 2, 1}, {{4, 4, 2}, 2, 1}, {{8, 8, 2}, 2, 1},
                              {{4, 4, 4}, 3, 2}};
-  const Cand* cand = c->ndim == 2 ? (c->f64() ? c2d : c2s) : (c->f64() ? c3d : c3s);
-  const int ncand = c->ndim == 2 ? (c->f64() ? 6 : 7) : (c->f64() ? 5 : 6);
+  const Cand* cand = c2s;
+  int ncand = (int)(sizeof c2s / sizeof c2s[0]);
+  if (c->ndim == 2 && c->f64()) {
+    cand = c2d;
+    ncand = (int)(sizeof c2d / sizeof c2d[0]);
+  } else if (c->ndim == 3) {
+    cand = c->f64() ? c3d : c3s;
+    ncand = c->f64() ? (int)(sizeof c3d / sizeof c3d[0]) : (int)(sizeof c3s / sizeof c3s[0]);
+  }
 
   // snapshot: the current particle store (the other one is the sort's
   // destination and holds nothing yet), fields, current, device state
