@@ -105,3 +105,35 @@ def test_autotune_arguments_and_state():
         assert ei.value.status == wt.PIC_ERR_STATE
     finally:
         sim.close()
+
+
+def test_autotune_keeps_the_time_of_the_skipped_calculation():
+    """With a partially skipped region set, the trial steps advance the
+    device's launch count that gives t; the restore puts it back, so A(t) of
+    the following steps is the one of a context that never tuned."""
+    spec = RunSpec(2, (96, 48), 2, 0.45, 50.0, 0.01, 4, 76)
+    sp, E, B = H.random_state(spec, 9, amp=0.05, fp32=False)
+    lo, hi = (40.0, 0.0), (48.0, 48.0)
+    a = wt.Sim([spec], wt.PIC_FP64)
+    b = wt.Sim([spec], wt.PIC_FP64)
+    try:
+        for sim in (a, b):
+            sim.set_species(0, sp)
+            sim.set_fields(0, E, B)
+            sim.set_skip_region(0, lo, hi, 0.0)
+        a.autotune(8)
+        a.step(10)
+        b.step(10)
+        xa = [a.particles(0, s) for s in range(2)]
+        xb = [b.particles(0, s) for s in range(2)]
+    finally:
+        a.close()
+        b.close()
+    # after 10 steps A(t) reaches c t = 4.5 cells beyond the strip: most
+    # particles still drift, a band of them took the full step
+    ex, eu = H.particle_errors(spec, [{"x": x, "u": u} for x, u in xb], xa)
+    print("skip + autotune vs default: dx=%.2e du=%.2e" % (ex, eu), flush=True)
+    assert ex <= 1e-12 and eu <= 1e-10
+    moved = sum(int(np.sum(np.any(xa[s][1] != sp[s]["u"], axis=1))) for s in range(2))
+    total = sum(len(sp[s]["u"]) for s in range(2))
+    assert 0 < moved < total
