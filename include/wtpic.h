@@ -70,7 +70,10 @@ typedef enum { PIC_FP64 = 0, PIC_MIXED32 = 1 } pic_precision;
  * parameters may differ (the batched time-step sweep). */
 typedef struct {
   int32_t ndim;             /* 2 or 3 */
-  int32_t n[3];             /* cells per axis; n[2] = 1 in 2D.  Each n >= order + 3 */
+  int32_t n[3];             /* cells per axis; n[2] = 1 in 2D.  Each n >= order + 3;
+                               at most 65535 per axis in 2D, and 2048 (x1, x2) and
+                               1024 (x3) in 3D (the packed cell index of the
+                               mixed-precision layout) */
   double dx[3];             /* cell sizes */
   double c;                 /* speed of light */
   double courant;           /* c dt / dx[0]; the time step is dt = courant dx[0] / c.
@@ -79,6 +82,12 @@ typedef struct {
   int32_t order;            /* B-spline order l, 1..4 (T_1..T_4 of Sec. 2) */
   int32_t scheme;           /* pic_scheme */
   int32_t solver;           /* pic_solver */
+  int32_t drift_axis;       /* axis of the beam drift, 0..ndim-1; 0 is x1, the
+                               beam direction of Sec. 2 and Appendix A.  The
+                               particle path does not depend on it: the WT and
+                               MC tensors treat every axis alike, and the
+                               caller's particles carry the drift.  Recorded
+                               for the caller and validated. */
   int32_t precision;        /* pic_precision */
   int32_t ppc_per_species;  /* particles per cell per species (electrons, positrons) */
   double q_over_m[2];       /* charge-to-mass ratio per species (e.g. -1, +1) */
@@ -213,6 +222,14 @@ pic_status pic_set_tiling(pic_ctx *ctx, const int32_t tile[3], int32_t margin, i
  * before the particles of every run and species are set; a trial's failure is
  * returned after the state and the previous tiling are restored. */
 pic_status pic_autotune(pic_ctx *ctx, int32_t trial_steps, int32_t chosen[5], double *best_ms);
+
+/* The autotuner's candidate list for a dimension and precision (host only,
+ * no context): *count receives the number of candidates, and out (host,
+ * cap x 5 int32, may be NULL when cap is 0) the first min(cap, *count) of
+ * them as tile[0], tile[1], tile[2], margin, sort_every (tile[2] = 1 in 2D),
+ * in the order pic_autotune tries them; the first is the default tiling.
+ * PIC_ERR_ARG for a NULL count, cap < 0, or ndim/precision out of range. */
+pic_status pic_tiling_candidates(int32_t ndim, int32_t precision, int32_t *out, int32_t cap, int32_t *count);
 
 /* Device timing of the gather-push-deposit kernel.  enable != 0 starts
  * recording a HIP event pair around every gather-push-deposit kernel launch

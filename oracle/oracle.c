@@ -34,6 +34,17 @@ double orc_W(int l, double y) {
   return ((y + h) * orc_W(l - 1, y + 0.5) + (h - y) * orc_W(l - 1, y - 0.5)) / l;
 }
 
+/* The same recurrence in extended precision (long double).  The deposit
+ * takes S1 - S0 from it: a transverse step of ~1e-4 cells changes the form
+ * factor by ~1e-4, and the difference of two FP64 values of order one would
+ * keep only ~1e-12 of it. */
+static long double W_ext(int l, long double y) {
+  if (l == 0) return (y >= -0.5L && y < 0.5L) ? 1.0L : 0.0L;
+  long double h = 0.5L * (l + 1);
+  if (y <= -h || y >= h) return 0.0L;
+  return ((y + h) * W_ext(l - 1, y + 0.5L) + (h - y) * W_ext(l - 1, y - 0.5L)) / l;
+}
+
 /* C_l(z) = integral of W_{l-1} over (-inf, z].  Since W_l(y) is the average
  * of W_{l-1} over [y-1/2, y+1/2], summing W_l(z - 1/2 - m) over m >= 0
  * telescopes to that integral. */
@@ -178,10 +189,11 @@ void orc_wrap(const orc_grid *g, double *x) {
 
 /* Adds the current of one macro-particle of charge Q moving x0 -> x1 during
  * one step.  S0, S1 are the form factors W_l on integer nodes at the old and
- * new positions; DS = S1 - S0.  The current density is the unique
- * combination of form-factor differences obeying the discrete continuity
- * equation (rho^{n+1} - rho^n)/dt + D.J = 0 with D the Gauss operator of
- * Eq. gauss; each component is a prefix sum along its own axis. */
+ * new positions; DS = S1 - S0, formed in extended precision.  The current
+ * density is the unique combination of form-factor differences obeying the
+ * discrete continuity equation (rho^{n+1} - rho^n)/dt + D.J = 0 with D the
+ * Gauss operator of Eq. gauss; each component is a prefix sum along its own
+ * axis. */
 void orc_deposit(orc_grid *g, const double *x0, const double *x1, double Q, double vz) {
   int l = g->order;
   double h = 0.5 * (l + 1);
@@ -197,10 +209,12 @@ void orc_deposit(orc_grid *g, const double *x0, const double *x1, double Q, doub
     cnt[d] = hi - lo[d] + 1;
     for (int k = 0; k < cnt[d]; ++k) {
       int m = lo[d] + k;
-      double s0 = orc_W(l, x0[d] - m);
-      double s1 = orc_W(l, x1[d] - m);
-      S0[d][k] = s0;
-      DS[d][k] = s1 - s0;
+      /* x - m is exact in extended precision; the difference keeps its
+       * relative precision however short the step */
+      long double s0 = W_ext(l, (long double)x0[d] - m);
+      long double s1 = W_ext(l, (long double)x1[d] - m);
+      S0[d][k] = (double)s0;
+      DS[d][k] = (double)(s1 - s0);
     }
   }
   long n0 = g->n[0], n1 = g->n[1];

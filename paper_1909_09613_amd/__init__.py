@@ -31,7 +31,8 @@ EXPORTED = [
     "pic_query_layout", "pic_init", "pic_set_particles", "pic_get_particles", "pic_set_fields",
     "pic_get_fields", "pic_gather_push_deposit", "pic_field_update", "pic_step", "pic_step_diag",
     "pic_diagnostics",
-    "pic_set_tiling", "pic_autotune", "pic_set_skip_region", "pic_kernel_timing", "pic_last_error", "pic_destroy", "pic_table_weights",
+    "pic_set_tiling", "pic_autotune", "pic_tiling_candidates", "pic_set_skip_region", "pic_kernel_timing",
+    "pic_last_error", "pic_destroy", "pic_table_weights",
 ]
 
 
@@ -39,7 +40,8 @@ class pic_run_desc(ctypes.Structure):
     _fields_ = [
         ("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double * 3),
         ("c", ctypes.c_double), ("courant", ctypes.c_double), ("order", ctypes.c_int32),
-        ("scheme", ctypes.c_int32), ("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("scheme", ctypes.c_int32), ("solver", ctypes.c_int32), ("drift_axis", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
         ("ppc_per_species", ctypes.c_int32), ("q_over_m", ctypes.c_double * 2),
         ("macro_charge", ctypes.c_double * 2),
     ]
@@ -104,6 +106,7 @@ def lib():
             "pic_set_skip_region": [vp, i32, dp, dp, ctypes.c_double],
             "pic_kernel_timing": [vp, i32, dp, ctypes.POINTER(i64)],
             "pic_autotune": [vp, i32, ctypes.POINTER(i32), dp],
+            "pic_tiling_candidates": [i32, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)],
             "pic_destroy": [vp],
             "pic_table_weights": [i32, i32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32),
                                   ctypes.POINTER(i32), dp],
@@ -142,6 +145,7 @@ def make_desc(spec, precision=PIC_MIXED32):
     d.order = spec.order
     d.scheme = spec.scheme
     d.solver = spec.solver
+    d.drift_axis = spec.drift_axis
     d.precision = precision
     d.ppc_per_species = spec.ppc_s
     for s, (qm, Q, _M) in enumerate(spec.species_constants()):
@@ -256,6 +260,17 @@ def pic_autotune(ctx, trial_steps=16):
     ms = ctypes.c_double()
     _check(lib().pic_autotune(ctx, trial_steps, ch, ctypes.byref(ms)), ctx)
     return {"tile": tuple(ch[0:3]), "margin": ch[3], "sort_every": ch[4], "ms_per_step": ms.value}
+
+
+def pic_tiling_candidates(ndim, precision):
+    """The autotuner's candidate tilings, in trial order (the first is the
+    default): list of dicts tile, margin, sort_every."""
+    n = ctypes.c_int32()
+    _check(lib().pic_tiling_candidates(ndim, precision, None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_int32 * (5 * max(n.value, 1)))()
+    _check(lib().pic_tiling_candidates(ndim, precision, buf, n.value, ctypes.byref(n)))
+    return [{"tile": tuple(buf[5 * i:5 * i + 3]), "margin": buf[5 * i + 3], "sort_every": buf[5 * i + 4]}
+            for i in range(n.value)]
 
 
 def pic_last_error(ctx=None):

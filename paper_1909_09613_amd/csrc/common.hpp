@@ -22,8 +22,12 @@ struct F64 {
   static constexpr bool kAbs = true;
 };
 
-// Packed cell coordinates of the FP32 layout: 2D x | y << 16 (n < 65536),
-// 3D x | y << 11 | z << 22 (n < 2048).
+// Packed cell coordinates of the FP32 layout: 2D x | y << 16 (16 bits per
+// axis), 3D x | y << 11 | z << 22 (11, 11 and 10 bits).  A coordinate must fit
+// its field, so a run has at most max_cells_per_axis cells along an axis.
+__host__ __device__ constexpr int max_cells_per_axis(int ndim, int axis) {
+  return ndim == 2 ? 65535 : (axis == 2 ? 1 << 10 : 1 << 11);
+}
 template <int DIM>
 __host__ __device__ inline int pack_cell(int x, int y, int z) {
   if (DIM == 2) return x | (y << 16);

@@ -91,13 +91,17 @@ bool validate(const pic_run_desc* runs, int n_runs, pic_status* st, std::string*
     if (d.ndim == 2 && d.n[2] != 1) return fail(PIC_ERR_ARG, "2D runs need n[2] == 1");
     double inv2 = 0.0;
     long long ncell = 1;
+    if (d.drift_axis < 0 || d.drift_axis >= d.ndim) return fail(PIC_ERR_ARG, "drift_axis must be in 0..ndim-1");
     for (int k = 0; k < d.ndim; ++k) {
-      const int lim = (d.ndim == 2) ? 65535 : 2047;
+      const int lim = max_cells_per_axis(d.ndim, k);
       if (d.n[k] < d.order + 3) {
         snprintf(buf, sizeof buf, "run %d: n[%d] = %d is smaller than order + 3", r, k, d.n[k]);
         return fail(PIC_ERR_ARG, buf);
       }
-      if (d.n[k] > lim) return fail(PIC_ERR_ARG, "grid too large for the packed cell index");
+      if (d.n[k] > lim) {
+        snprintf(buf, sizeof buf, "run %d: n[%d] = %d exceeds %d, the packed cell index's limit", r, k, d.n[k], lim);
+        return fail(PIC_ERR_ARG, buf);
+      }
       if (!(d.dx[k] > 0) || !std::isfinite(d.dx[k])) return fail(PIC_ERR_ARG, "dx must be positive");
       inv2 += 1.0 / (d.dx[k] * d.dx[k]);
       ncell *= d.n[k];
@@ -599,6 +603,28 @@ int read_parity(pic_ctx* c, pic_status* st) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   *st = c->hip(e, "read state");
   return ds.parity;
+}
+
+// Autotuner candidates: tile (cells), staging margin, sort cadence; the first
+// of each list is the default tiling of pic_init.
+struct Cand {
+  int t[3], margin, every;
+};
+int tuning_candidates(int ndim, bool f64, const Cand** out) {
+  static const Cand c2s[] = {{{32, 16, 1}, 3, 2}, {{16, 16, 1}, 3, 2}, {{16, 32, 1}, 3, 2}, {{64, 8, 1}, 3, 2},
+                             {{32, 8, 1}, 3, 2},  {{32, 16, 1}, 2, 1}, {{16, 16, 1}, 2, 1}};
+  static const Cand c2d[] = {{{16, 16, 1}, 3, 2}, {{16, 8, 1}, 3, 2}, {{32, 8, 1}, 3, 2},
+                             {{8, 16, 1}, 3, 2},  {{32, 16, 1}, 3, 2}, {{16, 16, 1}, 2, 1}};
+  static const Cand c3s[] = {{{8, 4, 4}, 2, 1}, {{8, 8, 2}, 2, 1}, {{4, 4, 4}, 2, 1},
+                             {{16, 4, 4}, 2, 1}, {{8, 8, 4}, 2, 1}, {{8, 4, 4}, 3, 2}};
+  static const Cand c3d[] = {{{4, 4, 4}, 2, 1}, {{8, 4, 4}, 2, 1}, {{4, 4, 2}, 2, 1}, {{8, 8, 2}, 2, 1},
+                             {{4, 4, 4}, 3, 2}};
+  if (ndim == 2) {
+    *out = f64 ? c2d : c2s;
+    return f64 ? (int)(sizeof c2d / sizeof c2d[0]) : (int)(sizeof c2s / sizeof c2s[0]);
+  }
+  *out = f64 ? c3d : c3s;
+  return f64 ? (int)(sizeof c3d / sizeof c3d[0]) : (int)(sizeof c3s / sizeof c3s[0]);
 }
 
 void drop_graph(pic_ctx* c) {
@@ -1109,27 +1135,8 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, int32_t chosen[5], doub
   if (c->started) return c->fail(PIC_ERR_STATE, "autotune must run before the first step");
   pic_status st = check_ready(c);
   if (st != PIC_OK) return st;
-  // tile (cells), staging margin, sort cadence; the first is the default
-  struct Cand {
-    int t[3], margin, every;
-  };
-  static const Cand c2s[] = {{{32, 16, 1}, 3, 2}, {{16, 16, 1}, 3, 2}, {{16, 32, 1}, 3, 2}, {{64, 8, 1}, 3, 2},
-                             {{32, 8, 1}, 3, 2},  {{32, 16, 1}, 2, 1}, {{16, 16, 1}, 2, 1}};
-  static const Cand c2d[] = {{{16, 16, 1}, 3, 2}, {{16, 8, 1}, 3, 2}, {{32, 8, 1}, 3, 2},
-                             {{8, 16, 1}, 3, 2},  {{32, 16, 1}, 3, 2}, {{16, 16, 1}, 2, 1}};
-  static const Cand c3s[] = {{{8, 4, 4}, 2, 1}, {{8, 8, 2}, 2, 1}, {{4, 4, 4}, 2, 1},
-                             {{16, 4, 4}, 2, 1}, {{8, 8, 4}, 2, 1}, {{8, 4, 4}, 3, 2}};
-  static const Cand c3d[] = {{{4, 4, 4}, 2, 1}, {{8, 4, 4}, 2, 1}, {{4, 4, 2}, 2, 1}, {{8, 8, 2}, 2, 1},
-                             {{4, 4, 4}, 3, 2}};
-  const Cand* cand = c2s;
-  int ncand = (int)(sizeof c2s / sizeof c2s[0]);
-  if (c->ndim == 2 && c->f64()) {
-    cand = c2d;
-    ncand = (int)(sizeof c2d / sizeof c2d[0]);
-  } else if (c->ndim == 3) {
-    cand = c->f64() ? c3d : c3s;
-    ncand = c->f64() ? (int)(sizeof c3d / sizeof c3d[0]) : (int)(sizeof c3s / sizeof c3s[0]);
-  }
+  const Cand* cand = nullptr;
+  const int ncand = tuning_candidates(c->ndim, c->f64(), &cand);
 
   // snapshot: the current particle store (the other one is the sort's
   // destination and holds nothing yet), fields, current, device state
@@ -1314,6 +1321,26 @@ pic_status pic_table_weights(int32_t l, int32_t kind, double a, double f, int32_
   *node_first = base + t.first;
   *count = t.K;
   for (int k = 0; k < t.K; ++k) weights[k] = w[k];
+  return PIC_OK;
+}
+
+pic_status pic_tiling_candidates(int32_t ndim, int32_t precision, int32_t* out, int32_t cap, int32_t* count) {
+  if (!count || (cap > 0 && !out) || cap < 0) {
+    g_err = "count must not be NULL, and out not NULL when cap > 0";
+    return PIC_ERR_ARG;
+  }
+  if ((ndim != 2 && ndim != 3) || (precision != PIC_FP64 && precision != PIC_MIXED32)) {
+    g_err = "ndim must be 2 or 3 and precision PIC_FP64 or PIC_MIXED32";
+    return PIC_ERR_ARG;
+  }
+  const Cand* cand = nullptr;
+  const int n = tuning_candidates(ndim, precision == PIC_FP64, &cand);
+  *count = n;
+  for (int i = 0; i < n && i < cap; ++i) {
+    for (int k = 0; k < 3; ++k) out[5 * i + k] = k < ndim ? cand[i].t[k] : 1;
+    out[5 * i + 3] = cand[i].margin;
+    out[5 * i + 4] = cand[i].every;
+  }
   return PIC_OK;
 }
 

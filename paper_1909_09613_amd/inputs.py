@@ -16,7 +16,8 @@ being run):
     with probability (1 + beta v'_x)/2, otherwise reflect it.  This is the
     reading under which the reflected sample carries the Jacobian
     (1 + beta v'_x); the inequality as printed selects the opposite branch;
-  * Lorentz boost along +x1: u_x = gamma0 (u'_x + beta0 gamma'), u_perp = u'_perp;
+  * Lorentz boost along +x1: u_x = gamma0 (u'_x + beta0 gamma'), u_perp = u'_perp
+    (or along another axis, ``drift_axis``, with the components relabelled);
   * macro charge |Q| = gamma0 Vc omega_pe^2 / ppc_s with omega_pe = c / d_e and
     d_e = ``skin_depth_cells`` cells (Table 1: 256 cells = 16 d_e), macro mass
     M = |Q|, q/m = -1 (electrons) and +1 (positrons).
@@ -42,6 +43,7 @@ class RunSpec:
     colocated: bool = True
     dx: tuple = field(default=(1.0, 1.0, 1.0))
     c: float = 1.0
+    drift_axis: int = 0           # axis of the drift (0 = x1, the paper's beam direction)
 
     @property
     def ncell(self):
@@ -76,8 +78,10 @@ def box_muller(rng, n):
     return z[:n]
 
 
-def drifting_momenta(rng, n, gamma0, u_th):
-    """(n, 3) momenta u = gamma v / c of a plasma drifting along +x1."""
+def drifting_momenta(rng, n, gamma0, u_th, axis=0):
+    """(n, 3) momenta u = gamma v / c of a plasma drifting along +x_axis
+    (axis 0 is x1).  The draws do not depend on the axis: the components are
+    drawn as for a drift along x1 and then relabelled."""
     up = box_muller(rng, 3 * n).reshape(3, n).T * u_th
     gp = np.sqrt(1.0 + np.sum(up * up, axis=1))
     beta0 = np.sqrt(1.0 - 1.0 / (gamma0 * gamma0))
@@ -87,6 +91,8 @@ def drifting_momenta(rng, n, gamma0, u_th):
     up[flip, 0] = -up[flip, 0]
     u = up.copy()
     u[:, 0] = gamma0 * (up[:, 0] + beta0 * gp)
+    if axis != 0:
+        u[:, [0, axis]] = u[:, [axis, 0]]
     return u
 
 
@@ -139,8 +145,8 @@ def make_species(spec, workers=None):
         xe[p0:p1] = stratified_positions(rng, spec, p0, p1)
         if not spec.colocated:
             xp[p0:p1] = stratified_positions(rng, spec, p0, p1)
-        ue[p0:p1] = drifting_momenta(rng, p1 - p0, spec.gamma0, spec.u_th)
-        up[p0:p1] = drifting_momenta(rng, p1 - p0, spec.gamma0, spec.u_th)
+        ue[p0:p1] = drifting_momenta(rng, p1 - p0, spec.gamma0, spec.u_th, spec.drift_axis)
+        up[p0:p1] = drifting_momenta(rng, p1 - p0, spec.gamma0, spec.u_th, spec.drift_axis)
 
     if workers is None:
         workers = min(16, os.cpu_count() or 1)

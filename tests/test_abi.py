@@ -129,3 +129,83 @@ def test_table_node_counts(L):
         assert len(wt.pic_table_weights(l, 2, 0.3, 0.2)[1]) == l + 1
         assert len(wt.pic_table_weights(l, 2, 0.5, 0.2)[1]) == l + 1
         assert len(wt.pic_table_weights(l, 2, 0.7, 0.2)[1]) == l + 2
+
+
+@pytest.mark.parametrize("axis,status", [(0, wt.PIC_OK), (1, wt.PIC_OK), (2, wt.PIC_ERR_ARG), (-1, wt.PIC_ERR_ARG)])
+def test_drift_axis_validated_2d(L, axis, status):
+    """The beam drifts along x1 in the paper (Sec. 2, Appendix A); any
+    simulated axis is accepted, and nothing else."""
+    assert _status([_desc(drift_axis=axis)]) == status
+
+
+def test_drift_axis_validated_3d(L):
+    for axis, status in ((0, wt.PIC_OK), (2, wt.PIC_OK), (3, wt.PIC_ERR_ARG)):
+        assert _status([_desc(ndim=3, n=(16, 16, 16), courant=0.5, drift_axis=axis)]) == status
+
+
+@pytest.mark.parametrize("n,status", [
+    ((2048, 16, 16), wt.PIC_OK), ((2049, 16, 16), wt.PIC_ERR_ARG),
+    ((16, 2048, 16), wt.PIC_OK), ((16, 2049, 16), wt.PIC_ERR_ARG),
+    ((16, 16, 1024), wt.PIC_OK), ((16, 16, 1025), wt.PIC_ERR_ARG),
+])
+def test_3d_grid_limits_of_the_packed_cell(L, n, status):
+    """The mixed-precision layout packs a 3D cell as x | y << 11 | z << 22:
+    11, 11 and 10 bits, so at most 2048, 2048 and 1024 cells per axis."""
+    assert _status([_desc(ndim=3, n=n, courant=0.5, precision=wt.PIC_MIXED32)]) == status
+
+
+def test_packed_cell_round_trip():
+    """pack_cell / unpack_cell of the library's own header round-trip every
+    corner of the accepted grid ranges (host build of the header with hipcc)."""
+    import shutil
+    import subprocess
+    import tempfile
+
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = r'''
+#include <cstdio>
+#include "common.hpp"
+using namespace wtpic;
+int main() {
+  int bad = 0;
+  const int n2[2] = {max_cells_per_axis(2, 0), max_cells_per_axis(2, 1)};
+  const int n3[3] = {max_cells_per_axis(3, 0), max_cells_per_axis(3, 1), max_cells_per_axis(3, 2)};
+  for (int x : {0, 1, n2[0] - 1}) for (int y : {0, 1, n2[1] - 1}) {
+    int a, b, c; unpack_cell<2>(pack_cell<2>(x, y, 0), a, b, c);
+    bad += (a != x) || (b != y) || (c != 0);
+  }
+  for (int x : {0, 1, n3[0] - 1}) for (int y : {0, 1, n3[1] - 1}) for (int z : {0, 1, n3[2] / 2, n3[2] - 1}) {
+    int a, b, c; unpack_cell<3>(pack_cell<3>(x, y, z), a, b, c);
+    bad += (a != x) || (b != y) || (c != z);
+  }
+  printf("%d %d %d %d %d %d\n", bad, n2[0], n3[0], n3[1], n3[2], 0);
+  return bad != 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        cpp = os.path.join(d, "rt.cpp")
+        exe = os.path.join(d, "rt")
+        with open(cpp, "w") as f:
+            f.write(src)
+        subprocess.run([hipcc, "-std=c++17", "-O1", "-I", os.path.join(root, "paper_1909_09613_amd", "csrc"),
+                        cpp, "-o", exe], check=True, capture_output=True)
+        out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout
+    assert out.stdout.split()[:5] == ["0", "65535", "2048", "2048", "1024"]
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32])
+def test_tiling_candidates_listed(L, ndim, precision):
+    cands = wt.pic_tiling_candidates(ndim, precision)
+    assert len(cands) >= 4
+    for c in cands:
+        assert all(t >= 2 for t in c["tile"][:ndim])
+        assert ndim == 3 or c["tile"][2] == 1
+        assert c["margin"] > c["sort_every"] >= 1
+    assert len({(c["tile"], c["margin"], c["sort_every"]) for c in cands}) == len(cands)
+    with pytest.raises(wt.PicError):
+        wt.pic_tiling_candidates(4, precision)
