@@ -233,11 +233,15 @@ pic_status pic_tiling_candidates(int32_t ndim, int32_t precision, int32_t *out, 
 
 /* Device timing of the gather-push-deposit kernel.  enable != 0 starts
  * recording a HIP event pair around every gather-push-deposit kernel launch
- * on the context stream (eager launches only; pic_step graphs are not
- * instrumented); enable == 0 stops.  On return *avg_ms holds the average
- * kernel time in milliseconds and *launches the number of launches recorded
- * since the previous call, which resets the record.  Synchronises the
- * stream. */
+ * on the context stream, eager launches and pic_step graph replays alike
+ * (the step graph is captured again with an event record before and after
+ * each particle-kernel node, and pic_step waits for every replay to read
+ * them, so the host does not run ahead of the device while timing is on);
+ * enable == 0 stops and drops the instrumented graph.  The events are
+ * created without the system-scope fence, so recording them flushes no
+ * cache.  On return *avg_ms holds the average kernel time in milliseconds
+ * and *launches the number of launches recorded since the previous call,
+ * which resets the record.  Synchronises the stream. */
 pic_status pic_kernel_timing(pic_ctx *ctx, int32_t enable, double *avg_ms, int64_t *launches);
 
 /* Text of the last error on this context (or of the last failed

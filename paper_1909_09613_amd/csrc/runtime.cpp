@@ -237,7 +237,14 @@ struct pic_ctx {
   hipGraph_t graph = nullptr;
   int graph_steps = 0;
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // eager launches since the last read
+  // graph-replayed launches: one event pair per particle-kernel node of the
+  // captured graph (re-recorded by every replay), and the sums read back
+  // after each replay
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> gevents;
+  int gevent_next = 0;
+  double graph_ms_sum = 0.0;
+  int64_t graph_launches = 0;
   std::vector<int> tile_run_host;
   std::vector<int> blk_run_host, blk_first_host;
 
@@ -553,18 +560,35 @@ pic_status enqueue_gpd(pic_ctx* c, bool capture) {
     if (e != hipSuccess) return c->hip(e, "sort launch");
     c->force_sort = false;
   }
-  const bool rec = c->timing && !capture;
+  // timing events take no system-scope fence: recording one would otherwise
+  // write back and invalidate the caches around every timed launch
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (rec) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    (void)hipEventRecord(e0, c->stream);
+  if (c->timing) {
+    if (capture) {
+      if (c->gevent_next >= (int)c->gevents.size()) {
+        std::pair<hipEvent_t, hipEvent_t> pr{nullptr, nullptr};
+        e = hipEventCreateWithFlags(&pr.first, hipEventDisableSystemFence);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pr.second, hipEventDisableSystemFence);
+        if (e != hipSuccess) return c->hip(e, "timing event");
+        c->gevents.push_back(pr);
+      }
+      e0 = c->gevents[c->gevent_next].first;
+      e1 = c->gevents[c->gevent_next].second;
+      ++c->gevent_next;
+    } else {
+      e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+      if (e != hipSuccess) return c->hip(e, "timing event");
+      c->events.emplace_back(e0, e1);
+    }
+    e = hipEventRecord(e0, c->stream);
+    if (e != hipSuccess) return c->hip(e, "timing event record");
   }
   e = launch_gpd<P>(gpd_args<Real>(c), c->order, c->ndim, c->lds, c->stream);
   if (e != hipSuccess) return c->hip(e, "gather-push-deposit launch");
-  if (rec) {
-    (void)hipEventRecord(e1, c->stream);
-    c->events.emplace_back(e0, e1);
+  if (c->timing) {
+    e = hipEventRecord(e1, c->stream);
+    if (e != hipSuccess) return c->hip(e, "timing event record");
   }
   c->step += 1;
   return PIC_OK;
@@ -633,6 +657,25 @@ void drop_graph(pic_ctx* c) {
   c->gexec = nullptr;
   c->graph = nullptr;
   c->graph_steps = 0;
+  for (auto& pr : c->gevents) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  c->gevents.clear();
+  c->gevent_next = 0;
+}
+
+// After a replay of an instrumented graph: waits for it and adds its
+// particle-kernel times to the record.
+pic_status read_graph_timing(pic_ctx* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  for (auto& pr : c->gevents) {
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    c->graph_ms_sum += ms;
+  }
+  c->graph_launches += (int64_t)c->gevents.size();
+  return c->hip(e, "graph timing");
 }
 
 }  // namespace
@@ -1074,6 +1117,7 @@ pic_status pic_step(pic_ctx* c, int32_t n_steps) {
     const bool aligned = !c->force_sort && c->step % c->sort_every == 0 && c->stream != nullptr;
     if (aligned && n_steps >= per_graph) {
       if (!c->gexec) {
+        drop_graph(c);
         hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return c->hip(e, "begin capture");
         const long long s0 = c->step;
@@ -1099,6 +1143,10 @@ pic_status pic_step(pic_ctx* c, int32_t n_steps) {
       }
       hipError_t e = hipGraphLaunch(c->gexec, c->stream);
       if (e != hipSuccess) return c->hip(e, "graph launch");
+      if (!c->gevents.empty()) {
+        st = read_graph_timing(c);
+        if (st != PIC_OK) return st;
+      }
       c->step += per_graph;
       n_steps -= per_graph;
       continue;
@@ -1258,17 +1306,21 @@ pic_status pic_kernel_timing(pic_ctx* c, int32_t enable, double* avg_ms, int64_t
   if (!c) return PIC_ERR_ARG;
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip(e, "timing sync");
-  double tot = 0.0;
+  double tot = c->graph_ms_sum;
   for (auto& pr : c->events) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) tot += ms;
     hipEventDestroy(pr.first);
     hipEventDestroy(pr.second);
   }
-  const int64_t n = (int64_t)c->events.size();
+  const int64_t n = (int64_t)c->events.size() + c->graph_launches;
   c->events.clear();
+  c->graph_ms_sum = 0.0;
+  c->graph_launches = 0;
   if (avg_ms) *avg_ms = n ? tot / n : 0.0;
   if (launches) *launches = n;
+  // the step graph carries event records only while timing is on
+  if ((enable != 0) != c->timing) drop_graph(c);
   c->timing = enable != 0;
   return PIC_OK;
 }

@@ -63,16 +63,20 @@ def transverse(spec, k):
 def current_tol(spec, k, fp32):
     """Tolerance of J component k against the summed scale.
 
-    Along the drift (and J3 in 2D): 1e-12 (FP64), 1e-5 (FP32).  Transverse
-    components are sums of Q * W * d over particles whose transverse steps d
-    are only ~ a u_th / gamma0 cells (mean |d| ~ 0.8 a u_th / gamma0 for a
-    Gaussian spread).  A position error e per particle gives a J error of
-    ~ e / mean|d| of the summed scale: e = 2^-25 cells for the FP32 offset the
-    step is taken from, e ~ 1e-15 cells for the oracle's own FP64 S1 - S0.
+    FP64: 1e-12 for every component.  The oracle forms S1 - S0 in extended
+    precision and the GPU as the step times a divided difference, so both
+    keep FP64 relative precision however short the step.
+
+    FP32: along the drift (and J3 in 2D) 1e-5.  Transverse components are
+    sums of Q * W * d over particles whose transverse steps d are only
+    ~ a u_th / gamma0 cells (mean |d| ~ 0.8 a u_th / gamma0 for a Gaussian
+    spread); a position error e per particle gives a J error of ~ e / mean|d|
+    of the summed scale, e = 2^-25 cells for the FP32 offset the step is taken
+    from.
     """
+    if not fp32:
+        return 1e-12
     if not transverse(spec, k):
-        return 1e-5 if fp32 else 1e-12
+        return 1e-5
     step = 0.8 * spec.courant * spec.u_th / spec.gamma0
-    if fp32:
-        return max(2e-4, 2.0 ** -25 / step)
-    return max(1e-11, 1e-15 / step)
+    return max(2e-4, 2.0 ** -25 / step)

@@ -11,11 +11,10 @@ not against the (possibly cancelled) total.
 
 Tolerances
   FP64, one step from identical state: positions 1e-12 cells, momenta 1e-12
-  relative, J 1e-12 of the summed scale for the components along the drift
-  (J1) and out of the plane (J3 in 2D).  The transverse components (J2 in
-  2D, J2 and J3 in 3D) carry steps of only |d| ~ a u_th / gamma0 ~ 1e-4
-  cells, and the oracle forms S1 - S0 from FP64 values of order one, so its
-  own rounding is ~4e-16 / |d| ~ 5e-12 of the summed scale: 1e-11.
+  relative, J 1e-12 of the summed scale for every component (the transverse
+  steps are only |d| ~ a u_th / gamma0 ~ 1e-4 cells; the oracle forms S1 - S0
+  in extended precision and the GPU as d times a divided difference, so
+  neither loses relative precision to the short step).
   FP32 mixed, from an FP32-representable state: positions 2e-6 cells,
   momenta 2e-6 relative; J1 (and J3 in 2D) 1e-5 of the summed scale;
   transverse components 2e-4: the new offset is stored in FP32 (rounding
@@ -48,14 +47,14 @@ def _oracle_current(orc, spec, sp, E, B):
     return out
 
 
-def _one_step(orc, spec, precision, seed=7, amp=0.05, tile=None):
+def _one_step(orc, spec, precision, seed=7, amp=0.05, tile=None, margin=0, sort_every=0):
     fp32 = precision == wt.PIC_MIXED32
     sp, E, B = H.random_state(spec, seed, amp, fp32=fp32)
     (g, ref), (ge, _), (gp, _) = _oracle_current(orc, spec, sp, E, B)
     sim = wt.Sim([spec], precision)
     try:
-        if tile is not None:
-            wt.pic_set_tiling(sim.ctx, tile, 0, 0)
+        if tile is not None or margin or sort_every:
+            wt.pic_set_tiling(sim.ctx, tile if tile is not None else (0, 0, 0), margin, sort_every)
         sim.set_species(0, sp)
         sim.set_fields(0, E, B)
         sim.gpd()
@@ -84,17 +83,21 @@ CASES_2D = [
     RunSpec(2, (32, 32), 2, 0.3, 50.0, 0.01, 3, 16, scheme=1),  # MC scheme
     # anisotropic cells: c dt/dx = 0.4 along x, 0.533 along y (l+1 and l+2 T nodes)
     RunSpec(2, (36, 28), 3, 0.4, 50.0, 0.01, 3, 17, dx=(1.0, 0.75, 1.0)),
+    # the beam along x2 instead of x1
+    RunSpec(2, (40, 36), 3, 0.45, 50.0, 0.01, 3, 18, drift_axis=1),
 ]
 CASES_3D = [
     RunSpec(3, (16, 12, 10), 2, 0.5, 50.0, 0.01, 2, 21),
     RunSpec(3, (14, 12, 11), 1, 0.4, 20.0, 0.05, 2, 22, colocated=False),
     RunSpec(3, (12, 12, 12), 3, 0.35, 50.0, 0.01, 1, 23),
     RunSpec(3, (14, 12, 10), 2, 0.3, 50.0, 0.01, 2, 24, dx=(1.0, 0.8, 1.25)),  # anisotropic cells
+    RunSpec(3, (12, 14, 16), 2, 0.45, 50.0, 0.01, 2, 25, drift_axis=2),        # the beam along x3
 ]
 
 
 def _ids(cases):
-    return ["%dd-l%d-a%.2f-%s" % (c.ndim, c.order, c.courant, "x".join(map(str, c.n))) for c in cases]
+    return ["%dd-l%d-a%.2f-%s%s" % (c.ndim, c.order, c.courant, "x".join(map(str, c.n)),
+                                    "-drift%d" % c.drift_axis if c.drift_axis else "") for c in cases]
 
 
 @pytest.mark.parametrize("spec", CASES_2D + CASES_3D, ids=_ids(CASES_2D + CASES_3D))
@@ -140,6 +143,33 @@ def test_one_step_explicit_tiling(orc, spec, precision, tile):
         assert ej[k] <= H.current_tol(spec, k, fp32)
 
 
+CANDIDATE_SPECS = {
+    # grids that every candidate tile divides unevenly in some direction
+    2: RunSpec(2, (70, 52), 3, 0.45, 50.0, 0.01, 3, 37),
+    3: RunSpec(3, (24, 20, 18), 2, 0.5, 50.0, 0.01, 2, 38),
+}
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("precision", [wt.PIC_MIXED32, wt.PIC_FP64], ids=["fp32", "fp64"])
+def test_one_step_every_autotune_candidate(orc, ndim, precision):
+    """Each tiling the autotuner may choose (tile shape, staging margin, sort
+    cadence; pic_tiling_candidates) gives the oracle's step to the one-step
+    bounds."""
+    fp32 = precision == wt.PIC_MIXED32
+    spec = CANDIDATE_SPECS[ndim]
+    cands = wt.pic_tiling_candidates(ndim, precision)
+    assert len(cands) >= 4
+    for i, c in enumerate(cands):
+        ex, eu, ej = _one_step(orc, spec, precision, seed=40 + i, tile=c["tile"], margin=c["margin"],
+                               sort_every=c["sort_every"])
+        print("candidate %s margin %d sort_every %d" % (c["tile"], c["margin"], c["sort_every"]), flush=True)
+        assert ex <= (2e-6 if fp32 else 1e-12)
+        assert eu <= (2e-6 if fp32 else 1e-12)
+        for k in range(3):
+            assert ej[k] <= H.current_tol(spec, k, fp32)
+
+
 @pytest.mark.parametrize("ndim,solver,aniso", [(2, 0, False), (2, 1, False), (3, 0, False), (3, 1, False),
                                                (2, 1, True), (3, 1, True)])
 @pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32])
@@ -173,8 +203,10 @@ def test_field_update(orc, ndim, solver, aniso, precision):
 
 def test_config1_trajectory_fp64(orc):
     """The 64x64 correctness workload (l = 2, c dt = 0.7 dx, 4 ppc/species,
-    gamma 50) for 100 full steps from the loader's state: particles, fields
-    and the field-energy history against the oracle."""
+    gamma 50) for 100 full steps from the loader's state, against the oracle
+    at the FP64 bound of 1e-12: particle positions (cells) and momenta
+    (relative), E and B (relative max-norm), the current of the last step
+    (summed scale of both species), and the field-energy history."""
     spec = inputs.config(1)[0]
     sp = inputs.make_species(spec)
     g = H.oracle_grid(orc, spec)
@@ -183,7 +215,7 @@ def test_config1_trajectory_fp64(orc):
     hist_o, hist_g = [], []
     try:
         sim.set_species(0, sp)
-        for n in range(100):
+        for n in range(99):
             g.step(ref)
             sim.gpd()
             sim.field_update()
@@ -192,6 +224,20 @@ def test_config1_trajectory_fp64(orc):
                 hist_o.append(UE.sum() + UB.sum())
                 d = sim.diagnostics(0)
                 hist_g.append(sum(d.UE) + sum(d.UB))
+        # step 100: its current is read before the field update clears it
+        scale = np.zeros((3, spec.ncell))
+        for s in range(2):
+            gs = H.oracle_grid(orc, spec)
+            gs.E[:] = g.E
+            gs.B[:] = g.B
+            gs.zero_J()
+            one = H.copy_species([ref[s]])[0]
+            gs.push_species(one["x"], one["u"], one["qm"], one["Q"])
+            scale += np.abs(gs.J)
+        g.step(ref)
+        sim.gpd()
+        _, _, Jg = sim.fields(0)
+        sim.field_update()
         got = [sim.particles(0, s) for s in range(2)]
         Eg, Bg, _ = sim.fields(0)
     finally:
@@ -199,11 +245,15 @@ def test_config1_trajectory_fp64(orc):
     ex, eu = H.particle_errors(spec, ref, got)
     eE = H.rel_maxnorm(Eg, g.E)
     eB = H.rel_maxnorm(Bg, g.B)
+    ej = [float(np.max(np.abs(Jg[k] - g.J[k])) / np.max(scale[k])) for k in range(3)]
     eh = np.max(np.abs(np.array(hist_g) / np.array(hist_o) - 1))
-    print("config1 100 steps: dx=%.2e du=%.2e dE=%s dB=%s dU=%.2e" % (ex, eu, eE, eB, eh), flush=True)
-    assert ex <= 1e-10
-    assert eu <= 1e-10
-    assert eh <= 1e-10
+    print("config1 100 steps: dx=%.2e du=%.2e dE=%s dB=%s dJ=%s dU=%.2e" % (
+        ex, eu, ["%.2e" % v for v in eE], ["%.2e" % v for v in eB], ["%.2e" % v for v in ej], eh), flush=True)
+    assert ex <= 1e-12
+    assert eu <= 1e-12
+    assert max(eE) <= 1e-12 and max(eB) <= 1e-12
+    assert max(ej) <= 1e-12
+    assert eh <= 1e-11
 
 
 def test_gauss_law_on_gpu(orc):

@@ -14,7 +14,8 @@ qualitatively, plus the FP32 path against the FP64 path:
 Workloads: 2D 256 x 128, l = 3, gamma0 = 50, u_th = 0.01, 8 particles per cell
 per species, run to t = 1500 dx/c (about 94 / omega_pe); and the paper's
 Table 1 problem (l = 4, 256 x 128, 32 per cell per species, gamma0 = 1000,
-k_B T = 0.01 m c^2) for the MC-limit statement.
+k_B T = 0.01 m c^2) with WT4 and MC4 at its five time steps, run to
+t = 1080 (the time of its spectrum snapshot).
 """
 import numpy as np
 import pytest
@@ -158,13 +159,60 @@ def test_fp32_matches_fp64_nci(runs, scheme):
     assert abs(U32.max() - U64.max()) <= 0.2 * U64.max()
 
 
-def test_table1_mc4_slowest_at_mc_limit():
-    """Table 1 problem with MC4 + Yee: dt = dt_CFL/sqrt(2) against 0.5 dt_CFL."""
+# ---- the paper's Table 1 problem, WT4 and MC4 with Yee, its five time steps ----
+
+TABLE1_RATIOS = (0.1, 0.3, 0.5, 0.7, 2 ** -0.5)   # dt / dt_CFL, dt_CFL = dx / (sqrt(2) c)
+TABLE1_T_END = 1080.0                              # the time of the paper's spectrum snapshot
+
+
+def _table1(scheme):
+    """l = 4, 256 x 128 cells (16 x 8 d_e), 32 particles per cell per
+    species, gamma0 = 1000, k_B T = 0.01 m c^2 (u_th = 0.1), Yee, run to
+    t = 1080 at each of the five time steps; E/E0 history per ratio."""
     out = {}
-    for r in (0.5, 2 ** -0.5):
-        spec = RunSpec(2, (256, 128), 4, r / np.sqrt(2.0), 1000.0, 0.1, 32, 91, scheme=wt.PIC_MC)
-        out[r] = _history(spec, wt.PIC_MIXED32, t_end=600.0)
-    (t1, U1, E0), (t2, U2, _) = out[0.5], out[2 ** -0.5]
-    print("table1 MC4: log10 E/E0 at t=600: dt=0.5 dt_CFL %.2f, dt_CFL/sqrt2 %.2f" % (
-        np.log10(U1[-1] / E0), np.log10(U2[-1] / E0)), flush=True)
-    assert np.log10(U1[-1] / U2[-1]) >= 3.0
+    for r in TABLE1_RATIOS:
+        spec = RunSpec(2, (256, 128), 4, r / np.sqrt(2.0), 1000.0, 0.1, 32, 91, scheme=scheme)
+        out[r] = _history(spec, wt.PIC_MIXED32, t_end=TABLE1_T_END)
+    for r, (t, U, E0) in out.items():
+        lv = np.log10(U / E0)
+        print("table1 %s dt/dt_CFL=%.3f: log10 E/E0 at t=100,300,600,1080: %.2f %.2f %.2f %.2f; "
+              "range over t>=200: %.2f .. %.2f" % (
+                  "WT4" if scheme == wt.PIC_WT else "MC4", r, np.log10(_at(t, U, 100) / E0),
+                  np.log10(_at(t, U, 300) / E0), np.log10(_at(t, U, 600) / E0), lv[-1],
+                  lv[t >= 200].min(), lv[t >= 200].max()), flush=True)
+    return out
+
+
+@pytest.fixture(scope="module")
+def table1_wt():
+    return _table1(wt.PIC_WT)
+
+
+@pytest.fixture(scope="module")
+def table1_mc():
+    return _table1(wt.PIC_MC)
+
+
+def test_table1_wt4_small_dt_stays_at_noise_level(table1_wt):
+    """Sec. 4: with WT4 + Yee at dt = 0.3 and 0.1 dt_CFL the field energy
+    stays between 1e-5 and 1e-4 of the initial kinetic energy for a long
+    time (here from t = 200, once the thermal noise has built up, to the
+    end at t = 1080)."""
+    for r in (0.1, 0.3):
+        t, U, E0 = table1_wt[r]
+        lv = U[t >= 200] / E0
+        assert lv.min() >= 1e-5 and lv.max() <= 1e-4, r
+
+
+def test_table1_wt4_level_falls_with_dt(table1_wt):
+    """Sec. 4: WT suppresses the NCI the better the smaller the time step."""
+    ends = [table1_wt[r][1][-1] / table1_wt[r][2] for r in (0.1, 0.3, 0.5, 0.7)]
+    assert all(a < b for a, b in zip(ends, ends[1:])), ends
+
+
+def test_table1_mc4_lowest_at_mc_limit(table1_mc):
+    """Sec. 4: MC4 + Yee has its lowest NCI at dt = dt_CFL / sqrt(2), where
+    the lowest-order growth rate vanishes (c dt = dx / 2)."""
+    best = table1_mc[2 ** -0.5][1][-1]
+    for r in (0.1, 0.3, 0.5, 0.7):
+        assert table1_mc[r][1][-1] > best, r
