@@ -18,8 +18,9 @@ replayed by pic_step from the captured step graph (median of five
 repetitions; inputs resident in HBM); `fp64` holds the same figures for the
 FP64 path, measured in the same run.  `roofline` refers to the dominant
 kernel, the gather-push-deposit kernel: its average launch time comes from
-HIP event records around each particle-kernel node of the captured step graph
-(pic_kernel_timing, on the context stream), and `achieved` is its algorithmic
+HIP events on the context stream around a graph holding that kernel alone,
+replayed once per step of K further steps (pic_kernel_timing; the sort checks
+and the field update run between the replays), and `achieved` is its algorithmic
 bytes per launch (particle state read and written once, E and B read and J
 written once per cell) over that time.  `traffic` is the HBM traffic per
 launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters stored under profiles/
@@ -364,8 +365,8 @@ def run_leg(args, specs, species, prec_name, check_runs):
             graph_ms.append(start.elapsed_time(stop))
         ms_graph = float(np.median(graph_ms))
 
-        # the particle kernel's own time: the same K graph-replayed steps with
-        # an event record around every particle-kernel node
+        # the particle kernel's own time: K more steps, each replaying a graph
+        # of the particle kernel alone between two stream events
         wt.pic_kernel_timing(sim.ctx, True)
         sim.step(args.steps)
         gpd_ms, launches = wt.pic_kernel_timing(sim.ctx, False)
@@ -417,7 +418,7 @@ def run_leg(args, specs, species, prec_name, check_runs):
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "valu": valu,
             "kernel": "gpd_kernel", "kernel_ms": gpd_ms, "launches": launches,
-            "kernel_timing": "HIP events around each particle-kernel node of the replayed step graph",
+            "kernel_timing": "HIP events around a one-kernel graph replayed once per step",
             "algorithmic_bytes_per_launch": alg_bytes, "source_digest": digest,
         },
         "graph_repetitions": len(graph_ms),

@@ -232,16 +232,16 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t trial_steps, int32_t chosen[5], do
 pic_status pic_tiling_candidates(int32_t ndim, int32_t precision, int32_t *out, int32_t cap, int32_t *count);
 
 /* Device timing of the gather-push-deposit kernel.  enable != 0 starts
- * recording a HIP event pair around every gather-push-deposit kernel launch
- * on the context stream, eager launches and pic_step graph replays alike
- * (the step graph is captured again with an event record before and after
- * each particle-kernel node, and pic_step waits for every replay to read
- * them, so the host does not run ahead of the device while timing is on);
- * enable == 0 stops and drops the instrumented graph.  The events are
- * created without the system-scope fence, so recording them flushes no
- * cache.  On return *avg_ms holds the average kernel time in milliseconds
- * and *launches the number of launches recorded since the previous call,
- * which resets the record.  Synchronises the stream. */
+ * recording a HIP event pair on the context stream around every
+ * gather-push-deposit kernel launch: eager launches of
+ * pic_gather_push_deposit, and in pic_step (which then takes its steps one
+ * by one instead of replaying the step graph) a graph holding the particle
+ * kernel alone, replayed once per step between the two events, with the
+ * sort checks and the field update launched around it.  enable == 0 stops.
+ * The events are created without the system-scope fence, so recording them
+ * flushes no cache.  On return *avg_ms holds the average kernel time in
+ * milliseconds and *launches the number of launches recorded since the
+ * previous call, which resets the record.  Synchronises the stream. */
 pic_status pic_kernel_timing(pic_ctx *ctx, int32_t enable, double *avg_ms, int64_t *launches);
 
 /* Text of the last error on this context (or of the last failed

@@ -46,6 +46,7 @@ struct Pair<double> {
   using T = double2;
 };
 
+
 // Sum over a 3D stencil of a staged component: weights along x, y, z are wx
 // (NX nodes), wy (NY), wz (NZ); ox, oy, oz the window index of the first node.
 template <int NX, int NY, int NZ, class Real>
@@ -89,12 +90,6 @@ __device__ __forceinline__ void lds_addq(int* p, float v) {
 __device__ __forceinline__ void lds_addq(int* p, double v) {
   atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)(int)floor(v));
 }
-// The same into a workgroup's private window in global memory.
-__device__ __forceinline__ void glob_addq(int* p, float v) {
-  int r;
-  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-  atomicAdd(reinterpret_cast<unsigned*>(p), (unsigned)r);
-}
 
 // Keeps a tile-constant integer in a vector register.  The particle loop
 // uses about twenty of them next to the run's tables; left to scalar
@@ -104,15 +99,10 @@ __device__ __forceinline__ int in_vgpr(int x) {
   return x;
 }
 
-// m mod n for -2n < m < 2n, without an integer division.  The box keeps
-// its centre in [0, n) and a cell index and a tile origin lie in [0, n), so
-// a particle's offset from the box's low end stays in that range.
-__device__ __forceinline__ int wrap_near(int m, int n) {
-  m += (m < 0) ? n : 0;
-  m += (m < 0) ? n : 0;
-  m -= (m >= n) ? n : 0;
-  return m;
-}
+// m mod n for -n <= m < n, without an integer division or a compare: the
+// sign bit selects n.  A cell index and the box's periodic low end, both
+// reduced to [0, n), differ by less than n.
+__device__ __forceinline__ int wrap_once(int m, int n) { return m + (n & (m >> 31)); }
 
 // 1 / sqrt(x) and 1 / x: hardware approximations (1 ulp) for FP32, IEEE for FP64.
 __device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -197,7 +187,7 @@ template <class P, int L, int DIM, int KT, bool SKIP>
 __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
                                          const RunDev<typename P::Real>* __restrict__ runs,
                                          const int* __restrict__ tile_run, const int g,
-                                         unsigned char* lds, int* sred) {
+                                         unsigned char* lds, int* sred, typename P::Real* spc) {
   using Real = typename P::Real;
   using Acc = typename P::Acc;
   using Real2 = typename Pair<Real>::T;
@@ -286,22 +276,27 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // (thr_c = 2 * the tile's largest m_c of the previous step, or of the
   // stored velocities after a sort) give a node value below 2^31 quanta;
   // the sums are taken modulo 2^32, so only the final value must fit.  A
-  // particle above a threshold deposits into a second set of fixed-point
-  // windows whose quantum uses the a-priori bound m_c < a_c (|v| < c; 1 for
-  // v3 in 2D), coarse but safe for any particle.
+  // component above its threshold goes to a second set of windows that
+  // accumulates in FP32 with floating-point atomics instead: slow per add,
+  // but such components are rare (a step more than twice the tile's largest
+  // of the previous step) and keep FP32's relative precision, where a
+  // fixed-point window sized for any particle (|v| < c) would round a
+  // thermal-scale contribution to a thousandth.
   constexpr bool kFix = !P::kAbs;
   // cell counts (the (l+3)^d cmax bound) only in 2D: a 3D tile holds fewer
   // particles than (l+3)^3 times its densest cell, so its bound is the tile's
   // particle count, and the LDS the counts would take buys 3D tiles room
   constexpr bool kCnt = kFix && DIM == 2;
-  // 3D keeps its coarse windows in a private region of global memory (only
-  // the rare components above their bound touch them), so that its LDS
+  // 3D keeps its coarse (FP32) windows in a private region of global memory
+  // (only the rare components above their bound touch them), so that its LDS
   // leaves room for three groups per CU
   constexpr bool kGlobCoarse = kFix && DIM == 3;
   Real qinv[3] = {Real(0), Real(0), Real(0)}, thr[3] = {Real(0), Real(0), Real(0)};
-  Real qcinv[3] = {Real(0), Real(0), Real(0)};
-  double qd[3] = {0.0, 0.0, 0.0}, qcd[3] = {0.0, 0.0, 0.0};
-  Real mnew[3] = {Real(0), Real(0), Real(0)};
+  double qd[3] = {0.0, 0.0, 0.0};
+  // largest step per component in this launch (>= 0, kept as the bit
+  // pattern of an FP32 value: integer max orders non-negative floats, and
+  // needs no NaN canonicalisation)
+  int mnew[3] = {0, 0, 0};
   if (kFix) {
     int reach = 1;
     for (int d = 0; d < DIM; ++d) reach *= L + 3;
@@ -315,13 +310,17 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         qd[c] = bnd / 2145386496.0;  // 2^31 (1 - 2^-10): room for rounding
         qinv[c] = Real(1.0 / qd[c]);
       }
-      const double amax = (DIM == 2 && c == 2) ? 1.0 : (double)R.a[c];
-      const double cbnd = nmax * jm * amax;
-      if (cbnd > 0.0) {
-        qcd[c] = cbnd / 2145386496.0;
-        qcinv[c] = Real(1.0 / qcd[c]);
-      }
     }
+  }
+
+  // species constants of the particle loop, one row per species in LDS (a
+  // particle's species is decided per lane, so its row is read with one LDS
+  // load rather than selected from registers): (q/m) dt / (2c) and the
+  // current scales, in fine quanta on the fixed-point path
+  if (tid < 2) {
+    spc[4 * tid] = R.eps[tid];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) spc[4 * tid + 1 + c] = kFix ? Real(R.js[tid][c]) * qinv[c] : Real(R.js[tid][c]);
   }
 
   Real2* P1 = nullptr;
@@ -340,10 +339,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     F6 = reinterpret_cast<Real*>(lds);
     Jl = reinterpret_cast<Acc*>(F6 + 6 * fcap);
   }
-  // fixed-point path: 3 fine and 3 coarse int windows, then (2D) the
-  // particle count per cell
+  // fixed-point path: 3 fine int windows and 3 coarse FP32 windows, then
+  // (2D) the particle count per cell
   int* Qf = reinterpret_cast<int*>(Jl);
-  int* Qc = kGlobCoarse ? A.coarse + (long long)blockIdx.x * A.coarse_cap : Qf + 3 * jcap;
+  float* Qc = kGlobCoarse ? reinterpret_cast<float*>(A.coarse + (long long)blockIdx.x * A.coarse_cap)
+                          : reinterpret_cast<float*>(Qf + 3 * jcap);
   int* Cw = Qf + 6 * jcap;
 
   // ---- stage E, B on the window; clear the current tile ------------------
@@ -399,7 +399,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     const int n = R.n[d];
     const int slack = max(0, n - 1 - (bb[2 * d + 1] - bb[2 * d]));
     const int lo = bb[2 * d] - (slack >> 1);
-    co[d] = pin(org[d] + lo);
+    co[d] = pin(wrapi(org[d] + lo, n));
     lo_[d] = pin(lo);
     nn[d] = pin(n);
     rlo[d] = pin(max(fo[d] - R.glo[d], jo[d] - R.dlo[d]));
@@ -457,13 +457,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         cw[d] = m;
       }
       // a drifting particle still bounds the next step's fixed-point scale
-      if (kFix) mnew[d] = fmax(mnew[d], fabs(ddd));
+      if (kFix) mnew[d] = max(mnew[d], __float_as_int((float)fabs(ddd)));
       const int rn = rel[d] + (cnd - c[d]);
       bmin[d] = min(bmin[d], rn);
       bmax[d] = max(bmax[d], rn);
       cwi += (rn - jo_[d]) * jws[d];
     }
-    if (kFix && DIM == 2) mnew[2] = fmax(mnew[2], fabs(vd[2]));
+    if (kFix && DIM == 2) mnew[2] = max(mnew[2], __float_as_int((float)fabs(vd[2])));
     if (kCnt) atomicAdd(Cw + cwi, 1);
     if (!P::kAbs) B.cell[p] = pack_cell<DIM>(cw[0], cw[1], cw[2]);
   };
@@ -508,7 +508,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         bool inwin = true;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-          const int rr = wrap_near(cc[k][d] - co[d], nn[d]) + lo_[d];
+          const int rr = wrap_once(cc[k][d] - co[d], nn[d]) + lo_[d];
           rel[d] = rr;
           inwin = inwin && rr >= rlo[d] && rr <= rhi[d];
         }
@@ -552,7 +552,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     for (int d = 0; d < DIM; ++d) {
       // periodic image nearest the box: rel in [lo, lo + n), the box centred
       // in that range (a box as wide as the axis starts it)
-      const int rr = wrap_near(c[d] - co[d], nn[d]) + lo_[d];
+      const int rr = wrap_once(c[d] - co[d], nn[d]) + lo_[d];
       rel[d] = rr;
       inwin = inwin && rr >= rlo[d] && rr <= rhi[d];
     }
@@ -643,7 +643,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     }
 
     // ---- Boris -------------------------------------------------------------
-    const Real eps = R.eps[sp];
+    const Real eps = spc[4 * sp];
     const Real umx = u0 + eps * E0, umy = u1 + eps * E1, umz = u2 + eps * E2;
     const Real igm = fast_rsqrt(Real(1) + umx * umx + umy * umy + umz * umz);
     const Real tx = eps * B0 * igm, ty = eps * B1 * igm, tz = eps * B2 * igm;
@@ -771,9 +771,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     // ---- Esirkepov current into the LDS tile -----------------------------
     // sink(c, i, v) adds v to component c at window index i; kx, ky, kz are
     // the current scales (-Q dx/(Vc dt) per axis, Q c / Vc for J3 in 2D),
-    // multiplied by the tile's fixed-point scale on the fixed-point path,
-    // and every value carries the offset o (one half there, else zero).
-    auto deposit = [&](auto sink, const Real kx, const Real ky, const Real kz, const Real o) {
+    // multiplied by the tile's fixed-point scale for a component that goes
+    // to a fixed-point window, and the values of component c carry the
+    // offset oc (one half there, else zero).
+    auto deposit = [&](auto sink, const Real kx, const Real ky, const Real kz, const Real ox, const Real oy,
+                       const Real oz) {
       if (DIM == 2) {
         // Slot L+1 of an axis (and the last prefix face along it) is nonzero
         // only when the particle's stencil widened along that axis.
@@ -782,7 +784,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           if (v == L + 1 && !cross[1]) continue;
           const Real fy = kx * (S0u[1][v] + half * DSu[1][v]);
           const int ro = iu[0] + jwx * (iu[1] + v);
-          Real acc = o;
+          Real acc = ox;
 #pragma unroll
           for (int u = 0; u < L; ++u) {
             acc += DSu[0][u] * fy;
@@ -795,7 +797,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           if (u == L + 1 && !cross[0]) continue;
           const Real fx = ky * (S0u[0][u] + half * DSu[0][u]);
           const int co = iu[0] + u + jwx * iu[1];
-          Real acc = o;
+          Real acc = oy;
 #pragma unroll
           for (int v = 0; v < L; ++v) {
             acc += DSu[1][v] * fx;
@@ -812,9 +814,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           const int ro = iu[0] + jwx * (iu[1] + v);
 #pragma unroll
           for (int u = 0; u <= L; ++u)
-            sink(2, ro + u, kFix ? fma(S0u[0][u], Av, fma(DSu[0][u], Bv, o)) : S0u[0][u] * Av + DSu[0][u] * Bv);
+            sink(2, ro + u, kFix ? fma(S0u[0][u], Av, fma(DSu[0][u], Bv, oz)) : S0u[0][u] * Av + DSu[0][u] * Bv);
           if (cross[0])
-            sink(2, ro + L + 1, kFix ? fma(S0u[0][L + 1], Av, fma(DSu[0][L + 1], Bv, o))
+            sink(2, ro + L + 1, kFix ? fma(S0u[0][L + 1], Av, fma(DSu[0][L + 1], Bv, oz))
                                      : S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv);
         }
       } else {
@@ -831,7 +833,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
             for (int u = 0; u <= L; ++u) {
               acc += DSu[0][u] * tr;
-              if (u < L || cross[0]) sink(0, ro + u, kFix ? fma(kx, acc, o) : kx * acc);
+              if (u < L || cross[0]) sink(0, ro + u, kFix ? fma(kx, acc, ox) : kx * acc);
             }
           }
         }
@@ -848,7 +850,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
             for (int v = 0; v <= L; ++v) {
               acc += DSu[1][v] * tr;
-              if (v < L || cross[1]) sink(1, co + jwx * v, kFix ? fma(ky, acc, o) : ky * acc);
+              if (v < L || cross[1]) sink(1, co + jwx * v, kFix ? fma(ky, acc, oy) : ky * acc);
             }
           }
         }
@@ -865,48 +867,41 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
             for (int w = 0; w <= L; ++w) {
               acc += DSu[2][w] * tr;
-              if (w < L || cross[2]) sink(2, co + jwx * jwy * w, kFix ? fma(kz, acc, o) : kz * acc);
+              if (w < L || cross[2]) sink(2, co + jwx * jwy * w, kFix ? fma(kz, acc, oz) : kz * acc);
             }
           }
         }
       }
     };
-    const Real jx = Real(R.js[sp][0]), jy = Real(R.js[sp][1]), jz = Real(R.js[sp][2]);
+    const Real ksp[3] = {spc[4 * sp + 1], spc[4 * sp + 2], spc[4 * sp + 3]};
     if (!kFix) {
-      deposit([&](int c, int i, Real v) { lds_add<Acc>(Jl + c * jcap + i, Acc(v)); }, jx, jy, jz, Real(0));
+      deposit([&](int c, int i, Real v) { lds_add<Acc>(Jl + c * jcap + i, Acc(v)); }, ksp[0], ksp[1], ksp[2],
+              Real(0), Real(0), Real(0));
     } else {
       // a component whose step (or |v3|) exceeds the tile's bound deposits
       // into the coarse windows, so that no fine node sum can overflow; the
       // particle's other components stay in the fine windows (a kick along
       // one axis leaves the others' precision alone)
       const Real m0 = fabs(dd[0]), m1 = fabs(dd[1]), m2 = (DIM == 2) ? fabs(vv[2]) : fabs(dd[2]);
-      mnew[0] = fmax(mnew[0], m0);
-      mnew[1] = fmax(mnew[1], m1);
-      mnew[2] = fmax(mnew[2], m2);
+      mnew[0] = max(mnew[0], __float_as_int((float)m0));
+      mnew[1] = max(mnew[1], __float_as_int((float)m1));
+      mnew[2] = max(mnew[2], __float_as_int((float)m2));
       if (m0 <= thr[0] && m1 <= thr[1] && m2 <= thr[2]) {
-        deposit([&](int c, int i, Real v) { lds_addq(Qf + c * jcap + i, v); },
-                jx * qinv[0], jy * qinv[1], jz * qinv[2], half);
+        deposit([&](int c, int i, Real v) { lds_addq(Qf + c * jcap + i, v); }, ksp[0], ksp[1], ksp[2], half, half,
+                half);
       } else {
         const bool f0 = m0 <= thr[0], f1 = m1 <= thr[1], f2 = m2 <= thr[2];
-        if constexpr (kGlobCoarse) {
-          sred[12] = 1;  // the flush reads the global coarse window
-          deposit(
-              [&](int c, int i, Real v) {
-                if (c == 0 ? f0 : (c == 1 ? f1 : f2))
-                  lds_addq(Qf + c * jcap + i, v);
-                else
-                  glob_addq(Qc + c * jcap + i, v);
-              },
-              jx * (f0 ? qinv[0] : qcinv[0]), jy * (f1 ? qinv[1] : qcinv[1]), jz * (f2 ? qinv[2] : qcinv[2]),
-              half);
-        } else {
-          int* const W0 = f0 ? Qf : Qc;
-          int* const W1 = (f1 ? Qf : Qc) + jcap;
-          int* const W2 = (f2 ? Qf : Qc) + 2 * jcap;
-          deposit([&](int c, int i, Real v) { lds_addq((c == 0 ? W0 : (c == 1 ? W1 : W2)) + i, v); },
-                  jx * (f0 ? qinv[0] : qcinv[0]), jy * (f1 ? qinv[1] : qcinv[1]),
-                  jz * (f2 ? qinv[2] : qcinv[2]), half);
-        }
+        const Real jx = Real(R.js[sp][0]), jy = Real(R.js[sp][1]), jz = Real(R.js[sp][2]);
+        if constexpr (kGlobCoarse) sred[12] = 1;  // the flush reads the global coarse window
+        deposit(
+            [&](int c, int i, Real v) {
+              if (c == 0 ? f0 : (c == 1 ? f1 : f2))
+                lds_addq(Qf + c * jcap + i, v);
+              else
+                atomicAdd(Qc + c * jcap + i, (float)v);
+            },
+            f0 ? jx * qinv[0] : jx, f1 ? jy * qinv[1] : jy, f2 ? jz * qinv[2] : jz, f0 ? half : Real(0),
+            f1 ? half : Real(0), f2 ? half : Real(0));
       }
     }
 
@@ -955,7 +950,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     noor += __shfl_xor(noor, off);
     if (kFix) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) mnew[c] = fmax(mnew[c], __shfl_xor(mnew[c], off));
+      for (int c = 0; c < 3; ++c) mnew[c] = max(mnew[c], __shfl_xor(mnew[c], off));
     }
   }
   if ((tid & 63) == 0) {
@@ -968,7 +963,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (noor) atomicAdd(&sred[7], noor);
     if (kFix) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) atomicMax(&sred[8 + c], __float_as_int((float)mnew[c]));
+      for (int c = 0; c < 3; ++c) atomicMax(&sred[8 + c], mnew[c]);
     }
   }
   __syncthreads();
@@ -1004,13 +999,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         if (coarse_used) {
           // the coarse sums were added at the L2; read them there and leave
           // the window zero for the group's next tile
-          int* q = Qc + c * jcap + li;
-          v += (double)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * qcd[c];
-          __hip_atomic_store(q, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          float* q = Qc + c * jcap + li;
+          v += (double)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(q, 0.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       } else {
-        v = kFix ? (double)Qf[c * jcap + li] * qd[c] + (double)Qc[c * jcap + li] * qcd[c]
-                 : (double)Jl[c * jcap + li];
+        v = kFix ? (double)Qf[c * jcap + li] * qd[c] + (double)Qc[c * jcap + li] : (double)Jl[c * jcap + li];
       }
       if (v != 0.0) unsafeAtomicAdd(Jg + c * NT + gi, v);
     }
@@ -1052,19 +1046,20 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 // Persistent workgroups: each takes tiles from a device queue until none are
 // left, so uneven tiles (edge tiles, runs of different size) balance.  The
 // queue starts at zero (set at initialisation, then rewound by the last
-// group of every launch).  The variant with the partially skipped
-// calculation is held to the plain kernel's occupancy (2D: four waves per
-// SIMD, two workgroups per CU; 3D: three): left alone it takes ~10 more
-// registers and drops a wave, which costs far more than the few spilled
-// values.
+// group of every launch).  In 2D every variant is held to four waves per
+// SIMD (two 512-thread workgroups per CU, at most 128 registers): a fifth
+// register block drops a wave and halves the workgroups a CU holds, which
+// costs far more than a few spilled values.  The 3D variant with the
+// partially skipped calculation is held to the plain kernel's three waves.
 template <class P, int L, int DIM, bool SKIP>
 __global__ void __launch_bounds__(gpd_block<DIM>())
-__attribute__((amdgpu_waves_per_eu(SKIP ? (DIM == 2 ? 4 : 3) : 1)))
+__attribute__((amdgpu_waves_per_eu(DIM == 2 ? 4 : (SKIP ? 3 : 1))))
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
                const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
   __shared__ int sred[13];
   __shared__ int next;
+  __shared__ __align__(32) typename P::Real spc[8];   // per-species constants of the tile's run
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(&A.st->tile_queue, 1);
     __syncthreads();
@@ -1082,9 +1077,9 @@ __attribute__((amdgpu_waves_per_eu(SKIP ? (DIM == 2 ? 4 : 3) : 1)))
     }
     const int kt = runs[tile_run[g]].KT;
     if (kt == L + 1)
-      gpd_tile<P, L, DIM, L + 1, SKIP>(A, runs, tile_run, g, lds_dyn, sred);
+      gpd_tile<P, L, DIM, L + 1, SKIP>(A, runs, tile_run, g, lds_dyn, sred, spc);
     else
-      gpd_tile<P, L, DIM, L + 2, SKIP>(A, runs, tile_run, g, lds_dyn, sred);
+      gpd_tile<P, L, DIM, L + 2, SKIP>(A, runs, tile_run, g, lds_dyn, sred, spc);
     __syncthreads();
   }
 }
@@ -1148,7 +1143,7 @@ __global__ void __launch_bounds__(256) rho_tiles_kernel(GpdArgs<typename P::Real
       fits = fits && jsz[d] >= 1 && jsz[d] <= A.jw[d];
       const int slack = max(0, R.n[d] - 1 - (bhi - blo));
       lo_[d] = blo - (slack >> 1);
-      co[d] = org[d] + lo_[d];
+      co[d] = wrapi(org[d] + lo_[d], R.n[d]);
       // a particle's nodes are rel + (base - cell) + first .. + L with
       // base - cell in {-1, 0}
       rlo[d] = jo[d] + 1 - R.Wi[d].first;
@@ -1187,7 +1182,7 @@ __global__ void __launch_bounds__(256) rho_tiles_kernel(GpdArgs<typename P::Real
         Real gg;
         tab_split(R.Wi[d], c[d], f[d], b, gg);
         tab_eval<L, L + 1, false>(R.Wi[d], gg, w[d]);
-        const int rel = wrap_near(c[d] - co[d], R.n[d]) + lo_[d];
+        const int rel = wrap_once(c[d] - co[d], R.n[d]) + lo_[d];
         inwin = inwin && rel >= rlo[d] && rel <= rhi[d];
         m[d] = rel + (b - c[d]) + R.Wi[d].first - jo[d];  // window index of the first node
         mg[d] = b + R.Wi[d].first;                        // its lattice index

@@ -237,14 +237,12 @@ struct pic_ctx {
   hipGraph_t graph = nullptr;
   int graph_steps = 0;
   bool timing = false;
+  bool use_gpd_graph = false;  // set by pic_step while timing
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // eager launches since the last read
-  // graph-replayed launches: one event pair per particle-kernel node of the
-  // captured graph (re-recorded by every replay), and the sums read back
-  // after each replay
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> gevents;
-  int gevent_next = 0;
-  double graph_ms_sum = 0.0;
-  int64_t graph_launches = 0;
+  // while timing: a graph of the particle kernel alone, replayed once per
+  // step between two stream events
+  hipGraphExec_t gexec_gpd = nullptr;
+  hipGraph_t graph_gpd = nullptr;
   std::vector<int> tile_run_host;
   std::vector<int> blk_run_host, blk_first_host;
 
@@ -560,33 +558,41 @@ pic_status enqueue_gpd(pic_ctx* c, bool capture) {
     if (e != hipSuccess) return c->hip(e, "sort launch");
     c->force_sort = false;
   }
-  // timing events take no system-scope fence: recording one would otherwise
-  // write back and invalidate the caches around every timed launch
+  // timing (never inside a capture): an event pair around the launch, which
+  // in pic_step is a replay of a graph holding the particle kernel alone.
+  // The events take no system-scope fence: recording one would otherwise
+  // write back and invalidate the caches around every timed launch.
+  const bool rec = c->timing && !capture;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing) {
-    if (capture) {
-      if (c->gevent_next >= (int)c->gevents.size()) {
-        std::pair<hipEvent_t, hipEvent_t> pr{nullptr, nullptr};
-        e = hipEventCreateWithFlags(&pr.first, hipEventDisableSystemFence);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&pr.second, hipEventDisableSystemFence);
-        if (e != hipSuccess) return c->hip(e, "timing event");
-        c->gevents.push_back(pr);
-      }
-      e0 = c->gevents[c->gevent_next].first;
-      e1 = c->gevents[c->gevent_next].second;
-      ++c->gevent_next;
-    } else {
-      e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
-      if (e != hipSuccess) return c->hip(e, "timing event");
-      c->events.emplace_back(e0, e1);
-    }
+  if (rec) {
+    e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    if (e != hipSuccess) return c->hip(e, "timing event");
+    c->events.emplace_back(e0, e1);
     e = hipEventRecord(e0, c->stream);
     if (e != hipSuccess) return c->hip(e, "timing event record");
   }
-  e = launch_gpd<P>(gpd_args<Real>(c), c->order, c->ndim, c->lds, c->stream);
+  if (rec && c->use_gpd_graph) {
+    if (!c->gexec_gpd) {
+      e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return c->hip(e, "begin capture");
+      const hipError_t el = launch_gpd<P>(gpd_args<Real>(c), c->order, c->ndim, c->lds, c->stream);
+      hipGraph_t gg = nullptr;
+      e = hipStreamEndCapture(c->stream, &gg);
+      if (el != hipSuccess || e != hipSuccess) {
+        if (gg) (void)hipGraphDestroy(gg);
+        return c->hip(el != hipSuccess ? el : e, "particle-kernel graph capture");
+      }
+      c->graph_gpd = gg;
+      e = hipGraphInstantiate(&c->gexec_gpd, gg, nullptr, nullptr, 0);
+      if (e != hipSuccess) return c->hip(e, "particle-kernel graph instantiate");
+    }
+    e = hipGraphLaunch(c->gexec_gpd, c->stream);
+  } else {
+    e = launch_gpd<P>(gpd_args<Real>(c), c->order, c->ndim, c->lds, c->stream);
+  }
   if (e != hipSuccess) return c->hip(e, "gather-push-deposit launch");
-  if (c->timing) {
+  if (rec) {
     e = hipEventRecord(e1, c->stream);
     if (e != hipSuccess) return c->hip(e, "timing event record");
   }
@@ -657,25 +663,10 @@ void drop_graph(pic_ctx* c) {
   c->gexec = nullptr;
   c->graph = nullptr;
   c->graph_steps = 0;
-  for (auto& pr : c->gevents) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
-  c->gevents.clear();
-  c->gevent_next = 0;
-}
-
-// After a replay of an instrumented graph: waits for it and adds its
-// particle-kernel times to the record.
-pic_status read_graph_timing(pic_ctx* c) {
-  hipError_t e = hipStreamSynchronize(c->stream);
-  for (auto& pr : c->gevents) {
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
-    c->graph_ms_sum += ms;
-  }
-  c->graph_launches += (int64_t)c->gevents.size();
-  return c->hip(e, "graph timing");
+  if (c->gexec_gpd) (void)hipGraphExecDestroy(c->gexec_gpd);
+  if (c->graph_gpd) (void)hipGraphDestroy(c->graph_gpd);
+  c->gexec_gpd = nullptr;
+  c->graph_gpd = nullptr;
 }
 
 }  // namespace
@@ -984,11 +975,24 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
   const int ncand = 6;
   c->margin = (c->ndim == 2) ? 3 : 2;
   c->sort_every = (c->ndim == 2) ? 2 : 1;
+  // the largest candidate that fits the budget and gives every persistent
+  // group a tile, down to tiles of 64 cells; a grid too small for that takes
+  // the smallest of those (a 256 x 128 grid has only 64 tiles of 32 x 16
+  // cells for 512 groups); smaller tiles only where the larger do not fit
   st = PIC_ERR_ARG;
   const size_t full = c->lds_budget;
   c->lds_budget = std::min(full, (size_t)kDefaultLds);
-  for (int i = 0; i < ncand && st != PIC_OK; ++i) {
+  int chosen = -1;
+  for (int i = 0; i < ncand; ++i) {
     const int* t = (c->ndim == 2) ? cand2[i] : cand3[i];
+    if (chosen >= 0 && t[0] * t[1] * t[2] < 64) break;
+    for (int k = 0; k < 3; ++k) c->tile[k] = t[k];
+    if ((c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c)) != PIC_OK) continue;
+    chosen = i;
+    if (c->G >= c->groups_plain) break;
+  }
+  if (chosen >= 0) {
+    const int* t = (c->ndim == 2) ? cand2[chosen] : cand3[chosen];
     for (int k = 0; k < 3; ++k) c->tile[k] = t[k];
     st = c->f64() ? apply_tiling<double>(c) : apply_tiling<float>(c);
   }
@@ -1113,11 +1117,21 @@ pic_status pic_step(pic_ctx* c, int32_t n_steps) {
   pic_status st = check_ready(c);
   if (st != PIC_OK) return st;
   const int per_graph = c->sort_every * std::max(1, 8 / c->sort_every);
+  if (c->timing && c->stream != nullptr) {
+    // timed steps: the particle kernel replayed from its own graph between
+    // two events, the sort checks and the field update launched around it
+    c->use_gpd_graph = true;
+    for (; n_steps > 0 && st == PIC_OK; --n_steps) {
+      st = do_gpd(c, false);
+      if (st == PIC_OK) st = do_fields(c);
+    }
+    c->use_gpd_graph = false;
+    return st;
+  }
   while (n_steps > 0) {
     const bool aligned = !c->force_sort && c->step % c->sort_every == 0 && c->stream != nullptr;
     if (aligned && n_steps >= per_graph) {
       if (!c->gexec) {
-        drop_graph(c);
         hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return c->hip(e, "begin capture");
         const long long s0 = c->step;
@@ -1143,10 +1157,6 @@ pic_status pic_step(pic_ctx* c, int32_t n_steps) {
       }
       hipError_t e = hipGraphLaunch(c->gexec, c->stream);
       if (e != hipSuccess) return c->hip(e, "graph launch");
-      if (!c->gevents.empty()) {
-        st = read_graph_timing(c);
-        if (st != PIC_OK) return st;
-      }
       c->step += per_graph;
       n_steps -= per_graph;
       continue;
@@ -1306,21 +1316,19 @@ pic_status pic_kernel_timing(pic_ctx* c, int32_t enable, double* avg_ms, int64_t
   if (!c) return PIC_ERR_ARG;
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip(e, "timing sync");
-  double tot = c->graph_ms_sum;
+  double tot = 0.0;
   for (auto& pr : c->events) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) tot += ms;
-    hipEventDestroy(pr.first);
-    hipEventDestroy(pr.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    tot += ms;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
   }
-  const int64_t n = (int64_t)c->events.size() + c->graph_launches;
+  const int64_t n = (int64_t)c->events.size();
   c->events.clear();
-  c->graph_ms_sum = 0.0;
-  c->graph_launches = 0;
+  if (e != hipSuccess) return c->hip(e, "kernel timing");
   if (avg_ms) *avg_ms = n ? tot / n : 0.0;
   if (launches) *launches = n;
-  // the step graph carries event records only while timing is on
-  if ((enable != 0) != c->timing) drop_graph(c);
   c->timing = enable != 0;
   return PIC_OK;
 }

@@ -36,12 +36,11 @@ __host__ __device__ inline void tab_split(const Tab<Real>& t, int cell, Real f, 
   if (t.sigma == Real(0)) {  // no split (folds away for constant tables)
     base = cell;
     g = f;
-  } else if (f >= t.sigma) {
-    base = cell;
-    g = f - t.sigma;
   } else {
-    base = cell - 1;
-    g = f + t.one_minus_sigma;
+    // selects rather than a branch: both sides are one instruction
+    const bool below = f < t.sigma;
+    base = cell - (below ? 1 : 0);
+    g = below ? f + t.one_minus_sigma : f - t.sigma;
   }
 }
 

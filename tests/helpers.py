@@ -56,8 +56,39 @@ def random_state(spec, seed, amp=0.05, fp32=False):
 
 
 def transverse(spec, k):
-    """Current components driven by the thermal (transverse) motion only."""
-    return k == 1 or (spec.ndim == 3 and k == 2)
+    """Current components along a simulated axis other than the drift's:
+    driven by the thermal motion only."""
+    return k < spec.ndim and k != spec.drift_axis
+
+
+def abs_current_scale(orc, spec, sp, E, B):
+    """Per component, the largest sum over a node of the absolute values of
+    the particles' contributions to it (the scale the rounding of a sum is
+    measured against).  One particle's contributions to J_k all have the sign
+    of Q d_k (its step along k, or Q v_z for J3 in 2D): a prefix sum of
+    S1 - S0 along k has one sign for a shift of the form factor, and the
+    transverse path averages are >= 0.  So the oracle's current of the
+    particles with Q u_k > 0, and that of the rest, give the sum of absolute
+    values as |J_k^+| + |J_k^-|."""
+    g = oracle_grid(orc, spec)
+    g.E[:] = E
+    g.B[:] = B
+    ref = copy_species(sp)
+    for s in ref:
+        g.push_species(s["x"], s["u"], s["qm"], s["Q"])
+    scale = np.zeros((3, spec.ncell))
+    for k in range(3):
+        for sign in (1.0, -1.0):
+            gk = oracle_grid(orc, spec)
+            gk.E[:] = E
+            gk.B[:] = B
+            gk.zero_J()
+            for s, s_new in zip(sp, ref):
+                mask = sign * s["Q"] * s_new["u"][:, k] > 0
+                if np.any(mask):
+                    gk.push_species(s["x"][mask].copy(), s["u"][mask].copy(), s["qm"], s["Q"])
+            scale[k] += np.abs(gk.J[k])
+    return np.max(scale, axis=1)
 
 
 def current_tol(spec, k, fp32):
@@ -67,12 +98,12 @@ def current_tol(spec, k, fp32):
     precision and the GPU as the step times a divided difference, so both
     keep FP64 relative precision however short the step.
 
-    FP32: along the drift (and J3 in 2D) 1e-5.  Transverse components are
-    sums of Q * W * d over particles whose transverse steps d are only
+    FP32 (against the sum of absolute contributions, abs_current_scale):
+    along the drift (and J3 in 2D) 1e-5.  Transverse components are sums of
+    Q * W * d over particles whose transverse steps d are only
     ~ a u_th / gamma0 cells (mean |d| ~ 0.8 a u_th / gamma0 for a Gaussian
     spread); a position error e per particle gives a J error of ~ e / mean|d|
-    of the summed scale, e = 2^-25 cells for the FP32 offset the step is taken
-    from.
+    of the scale, e = 2^-25 cells for the FP32 offset the step is taken from.
     """
     if not fp32:
         return 1e-12
