@@ -127,6 +127,23 @@ pic_status pic_query_layout(const pic_run_desc *runs, int32_t n_runs, size_t byt
 pic_status pic_init(const pic_run_desc *runs, int32_t n_runs, const pic_buffers *bufs,
                     void *hip_stream, pic_ctx **out);
 
+/* pic_init for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * context, but its scratch buffer is a file-scope device array of the
+ * library, 64 MiB on each device that uses it (held until the process
+ * ends), instead of bufs->scratch, which is ignored (bufs->bytes[3] too).
+ * The caller still provides the particle, field and current buffers.  The
+ * call allocates no device memory (no hipMalloc or hipFree, no allocating
+ * library routine).  There is one such array per device, so at most one
+ * context of this call may be alive per device: a second call on a device
+ * whose array is in use returns PIC_ERR_STATE until the first context is
+ * destroyed.  Runs whose scratch (pic_query_layout, bytes_out[3]) exceeds
+ * 64 MiB are refused with PIC_ERR_ARG (e.g. 3D mixed precision, whose coarse
+ * current windows alone take 335 MB; 2D runs of up to about 14M particles
+ * fit).  Otherwise as pic_init. */
+pic_status pic_init_static(const pic_run_desc *runs, int32_t n_runs, const pic_buffers *bufs,
+                           void *hip_stream, pic_ctx **out);
+
 /* Uploads one species of one run: x is host [n][3] positions in cell units
  * (entries past ndim ignored), u host [n][3] momenta u = gamma v / c; n must
  * equal ppc_per_species * ncell.  Positions are wrapped into [0, n_d).  The

@@ -28,7 +28,7 @@ STATUS_NAMES = {
 }
 
 EXPORTED = [
-    "pic_query_layout", "pic_init", "pic_set_particles", "pic_get_particles", "pic_set_fields",
+    "pic_query_layout", "pic_init", "pic_init_static", "pic_set_particles", "pic_get_particles", "pic_set_fields",
     "pic_get_fields", "pic_gather_push_deposit", "pic_field_update", "pic_step", "pic_step_diag",
     "pic_diagnostics",
     "pic_set_tiling", "pic_autotune", "pic_tiling_candidates", "pic_set_skip_region", "pic_kernel_timing",
@@ -93,6 +93,7 @@ def lib():
         sig = {
             "pic_query_layout": [rd, i32, ctypes.POINTER(ctypes.c_size_t)],
             "pic_init": [rd, i32, ctypes.POINTER(pic_buffers), vp, ctypes.POINTER(vp)],
+            "pic_init_static": [rd, i32, ctypes.POINTER(pic_buffers), vp, ctypes.POINTER(vp)],
             "pic_set_particles": [vp, i32, i32, dp, dp, i64],
             "pic_get_particles": [vp, i32, i32, dp, dp, i64],
             "pic_set_fields": [vp, i32, dp, dp],
@@ -167,6 +168,16 @@ def pic_init(descs, bufs, stream_handle):
     arr = (pic_run_desc * len(descs))(*descs)
     ctx = ctypes.c_void_p()
     _check(lib().pic_init(arr, len(descs), ctypes.byref(bufs), ctypes.c_void_p(stream_handle), ctypes.byref(ctx)))
+    return ctx
+
+
+def pic_init_static(descs, bufs, stream_handle):
+    """pic_init with the library's static device scratch (bufs.scratch is
+    ignored)."""
+    arr = (pic_run_desc * len(descs))(*descs)
+    ctx = ctypes.c_void_p()
+    _check(lib().pic_init_static(arr, len(descs), ctypes.byref(bufs), ctypes.c_void_p(stream_handle),
+                                 ctypes.byref(ctx)))
     return ctx
 
 

@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libwtpic.so")
 SOURCES = [
     ("tables.cpp", "tables", []), ("runtime.cpp", "runtime", []),
     ("gpd.hip", "gpd32", ["-DWTPIC_GPD_POLICY=32"]), ("gpd.hip", "gpd64", ["-DWTPIC_GPD_POLICY=64"]),
-    ("sort.hip", "sort", []), ("fields.hip", "fields", []),
+    ("sort.hip", "sort", []), ("fields.hip", "fields", []), ("static_scratch.hip", "static_scratch", []),
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -3,9 +3,16 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/wtpic.h"
 #include "common.hpp"
 
 namespace wtpic {
+
+// Internal hooks of the allocation-free initialisation (static_scratch.hip):
+// a function pic_destroy calls with arg once the context's stream has
+// drained, and the text pic_last_error(NULL) returns.
+void set_destroy_hook(pic_ctx* c, void (*hook)(int), int arg);
+void set_global_error(const char* msg);
 
 template <class Real>
 struct SortArgs {

@@ -245,6 +245,10 @@ struct pic_ctx {
   hipGraph_t graph_gpd = nullptr;
   std::vector<int> tile_run_host;
   std::vector<int> blk_run_host, blk_first_host;
+  // called by pic_destroy once the stream has drained (allocation-free
+  // initialisation: releases the device's static scratch)
+  void (*destroy_hook)(int) = nullptr;
+  int destroy_hook_arg = -1;
 
   pic_status fail(pic_status s, const std::string& m) {
     err = m;
@@ -875,6 +879,17 @@ pic_status diag_t(pic_ctx* c, int run, pic_diag* out) {
 
 }  // namespace
 
+namespace wtpic {
+
+void set_destroy_hook(pic_ctx* c, void (*hook)(int), int arg) {
+  c->destroy_hook = hook;
+  c->destroy_hook_arg = arg;
+}
+
+void set_global_error(const char* msg) { g_err = msg; }
+
+}  // namespace wtpic
+
 extern "C" {
 
 pic_status pic_query_layout(const pic_run_desc* runs, int32_t n_runs, size_t bytes_out[4]) {
@@ -1343,6 +1358,7 @@ pic_status pic_destroy(pic_ctx* c) {
     hipEventDestroy(pr.first);
     hipEventDestroy(pr.second);
   }
+  if (c->destroy_hook) c->destroy_hook(c->destroy_hook_arg);
   delete c;
   return PIC_OK;
 }
