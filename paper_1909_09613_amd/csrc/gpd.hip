@@ -48,9 +48,10 @@ struct Pair<double> {
 
 
 // Sum over a 3D stencil of a staged component: weights along x, y, z are wx
-// (NX nodes), wy (NY), wz (NZ); ox, oy, oz the window index of the first node.
+// (NX nodes), wy (NY), wz (NZ); ox, oy, oz the window index of the first node;
+// px, pz the window's row and plane pitch.
 template <int NX, int NY, int NZ, class Real>
-__device__ __forceinline__ Real gather3(const Real* Fc, int fwx, int fwy, const Real* wx, const Real* wy,
+__device__ __forceinline__ Real gather3(const Real* Fc, int px, int pz, const Real* wx, const Real* wy,
                                         const Real* wz, int ox, int oy, int oz) {
   Real s = Real(0);
 #pragma unroll
@@ -58,7 +59,7 @@ __device__ __forceinline__ Real gather3(const Real* Fc, int fwx, int fwy, const 
     Real sy = Real(0);
 #pragma unroll
     for (int j = 0; j < NY; ++j) {
-      const Real* row = Fc + ox + fwx * (oy + j + fwy * (oz + k));
+      const Real* row = Fc + ox + px * (oy + j) + pz * (oz + k);
       Real sx = Real(0);
 #pragma unroll
       for (int i = 0; i < NX; ++i) sx += wx[i] * row[i];
@@ -183,7 +184,7 @@ constexpr int gpd_block() {
   return DIM == 2 ? 512 : 256;
 }
 
-template <class P, int L, int DIM, int KT, bool SKIP>
+template <class P, int L, int DIM, int KT, bool SKIP, int CP>
 __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
                                          const RunDev<typename P::Real>* __restrict__ runs,
                                          const int* __restrict__ tile_run, const int g,
@@ -256,10 +257,15 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       smode = 2;
   }
 
-  const int fwx = A.fw[0], fwy = A.fw[1];
-  const int fcap = fwx * fwy * (DIM == 3 ? A.fw[2] : 1);
-  const int jwx = A.jw[0], jwy = A.jw[1];
-  const int jcap = jwx * jwy * (DIM == 3 ? A.jw[2] : 1);
+  // windows: index x + row pitch * y + plane pitch * z (the pitches may
+  // exceed the extents, so that the rows a wave reads at once spread over
+  // the LDS banks)
+  // (CP > 0: the row pitch is that compile-time constant, so that the rows
+  // of a stencil are immediate offsets from one address)
+  const int fpx = CP > 0 ? CP : A.fp[0], fpz = A.fp[1];
+  const int fcap = (DIM == 3) ? fpz * A.fw[2] : fpx * A.fw[1];
+  const int jpx = CP > 0 ? CP : A.jp[0], jpz = A.jp[1];
+  const int jcap = (DIM == 3) ? jpz * A.jw[2] : jpx * A.jw[1];
   const long long NT = A.ncell_total;
   const Real* Fg = A.F + R.cell0;
 
@@ -357,7 +363,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     const int gy = wrapi(org[1] + fo[1] + w1, R.n[1]);
     const int gz = (DIM == 3) ? wrapi(org[2] + fo[2] + w2, R.n[2]) : 0;
     const long long gi = gx + (long long)R.n[0] * (gy + (long long)R.n[1] * gz);
-    const int li = w0 + fwx * (w1 + fwy * w2);
+    const int li = w0 + fpx * w1 + fpz * w2;
     if (DIM == 2) {
       Real2 a, b;
       a.x = Fg[0 * NT + gi];
@@ -408,7 +414,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     toff[d] = pin(R.T[d].first - fo[d]);
     uoff[d] = pin(R.Wi[d].first - jo[d]);
     jo_[d] = pin(jo[d]);
-    jws[d] = pin(d == 0 ? 1 : (d == 1 ? A.jw[0] : A.jw[0] * A.jw[1]));
+    jws[d] = pin(d == 0 ? 1 : (d == 1 ? jpx : jpz));
   }
 
   // partially skipped calculation: outside the perturbed region a particle
@@ -604,7 +610,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       E0 = B1 = Real(0);
 #pragma unroll
       for (int j = 0; j < KT; ++j) {
-        const Real2* row = P1 + ih[0] + fwx * (it[1] + j);
+        const Real2* row = P1 + ih[0] + fpx * (it[1] + j);
         Real se = Real(0), sb = Real(0);
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
@@ -619,7 +625,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       E1 = B0 = Real(0);
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        const Real2* row = P2 + it[0] + fwx * (ih[1] + j);
+        const Real2* row = P2 + it[0] + fpx * (ih[1] + j);
         Real se = Real(0), sb = Real(0);
 #pragma unroll
         for (int i = 0; i < KT; ++i) {
@@ -631,15 +637,15 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         B0 += wh[1][j] * sb;
       }
       const Real one = Real(1);
-      E2 = gather3<KT, KT, 1>(P3, fwx, fwy, wt[0], wt[1], &one, it[0], it[1], 0);
-      B2 = gather3<NW, NW, 1>(P4, fwx, fwy, wh[0], wh[1], &one, ih[0], ih[1], 0);
+      E2 = gather3<KT, KT, 1>(P3, fpx, fpz, wt[0], wt[1], &one, it[0], it[1], 0);
+      B2 = gather3<NW, NW, 1>(P4, fpx, fpz, wh[0], wh[1], &one, ih[0], ih[1], 0);
     } else {
-      E0 = gather3<NW, KT, KT>(F6 + 0 * fcap, fwx, fwy, wh[0], wt[1], wt[2], ih[0], it[1], it[2]);
-      E1 = gather3<KT, NW, KT>(F6 + 1 * fcap, fwx, fwy, wt[0], wh[1], wt[2], it[0], ih[1], it[2]);
-      E2 = gather3<KT, KT, NW>(F6 + 2 * fcap, fwx, fwy, wt[0], wt[1], wh[2], it[0], it[1], ih[2]);
-      B0 = gather3<KT, NW, NW>(F6 + 3 * fcap, fwx, fwy, wt[0], wh[1], wh[2], it[0], ih[1], ih[2]);
-      B1 = gather3<NW, KT, NW>(F6 + 4 * fcap, fwx, fwy, wh[0], wt[1], wh[2], ih[0], it[1], ih[2]);
-      B2 = gather3<NW, NW, KT>(F6 + 5 * fcap, fwx, fwy, wh[0], wh[1], wt[2], ih[0], ih[1], it[2]);
+      E0 = gather3<NW, KT, KT>(F6 + 0 * fcap, fpx, fpz, wh[0], wt[1], wt[2], ih[0], it[1], it[2]);
+      E1 = gather3<KT, NW, KT>(F6 + 1 * fcap, fpx, fpz, wt[0], wh[1], wt[2], it[0], ih[1], it[2]);
+      E2 = gather3<KT, KT, NW>(F6 + 2 * fcap, fpx, fpz, wt[0], wt[1], wh[2], it[0], it[1], ih[2]);
+      B0 = gather3<KT, NW, NW>(F6 + 3 * fcap, fpx, fpz, wt[0], wh[1], wh[2], it[0], ih[1], ih[2]);
+      B1 = gather3<NW, KT, NW>(F6 + 4 * fcap, fpx, fpz, wh[0], wt[1], wh[2], ih[0], it[1], ih[2]);
+      B2 = gather3<NW, NW, KT>(F6 + 5 * fcap, fpx, fpz, wh[0], wh[1], wt[2], ih[0], ih[1], it[2]);
     }
 
     // ---- Boris -------------------------------------------------------------
@@ -774,8 +780,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     // multiplied by the tile's fixed-point scale for a component that goes
     // to a fixed-point window, and the values of component c carry the
     // offset oc (one half there, else zero).
+    // Window indices are jb (the particle's first union node) plus offsets
+    // that are the same for every lane (uniform, or immediates when the row
+    // pitch is a compile-time constant), so a row costs one add at most.
     auto deposit = [&](auto sink, const Real kx, const Real ky, const Real kz, const Real ox, const Real oy,
                        const Real oz) {
+      const int jb = iu[0] + jpx * iu[1] + (DIM == 3 ? jpz * iu[2] : 0);
       if (DIM == 2) {
         // Slot L+1 of an axis (and the last prefix face along it) is nonzero
         // only when the particle's stencil widened along that axis.
@@ -783,27 +793,26 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         for (int v = 0; v < NU; ++v) {
           if (v == L + 1 && !cross[1]) continue;
           const Real fy = kx * (S0u[1][v] + half * DSu[1][v]);
-          const int ro = iu[0] + jwx * (iu[1] + v);
+          const int ro = jpx * v;
           Real acc = ox;
 #pragma unroll
           for (int u = 0; u < L; ++u) {
             acc += DSu[0][u] * fy;
-            sink(0, ro + u, acc);
+            sink(0, jb + (ro + u), acc);
           }
-          if (cross[0]) sink(0, ro + L, acc + DSu[0][L] * fy);
+          if (cross[0]) sink(0, jb + (ro + L), acc + DSu[0][L] * fy);
         }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           if (u == L + 1 && !cross[0]) continue;
           const Real fx = ky * (S0u[0][u] + half * DSu[0][u]);
-          const int co = iu[0] + u + jwx * iu[1];
           Real acc = oy;
 #pragma unroll
           for (int v = 0; v < L; ++v) {
             acc += DSu[1][v] * fx;
-            sink(1, co + jwx * v, acc);
+            sink(1, jb + (u + jpx * v), acc);
           }
-          if (cross[1]) sink(1, co + jwx * L, acc + DSu[1][L] * fx);
+          if (cross[1]) sink(1, jb + (u + jpx * L), acc + DSu[1][L] * fx);
         }
         const Real vz = kz * vv[2];
 #pragma unroll
@@ -811,29 +820,39 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           if (v == L + 1 && !cross[1]) continue;
           const Real Av = vz * (S0u[1][v] + half * DSu[1][v]);
           const Real Bv = vz * (half * S0u[1][v] + third * DSu[1][v]);
-          const int ro = iu[0] + jwx * (iu[1] + v);
+          const int ro = jpx * v;
 #pragma unroll
           for (int u = 0; u <= L; ++u)
-            sink(2, ro + u, kFix ? fma(S0u[0][u], Av, fma(DSu[0][u], Bv, oz)) : S0u[0][u] * Av + DSu[0][u] * Bv);
+            sink(2, jb + (ro + u),
+                 kFix ? fma(S0u[0][u], Av, fma(DSu[0][u], Bv, oz)) : S0u[0][u] * Av + DSu[0][u] * Bv);
           if (cross[0])
-            sink(2, ro + L + 1, kFix ? fma(S0u[0][L + 1], Av, fma(DSu[0][L + 1], Bv, oz))
-                                     : S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv);
+            sink(2, jb + (ro + L + 1), kFix ? fma(S0u[0][L + 1], Av, fma(DSu[0][L + 1], Bv, oz))
+                                            : S0u[0][L + 1] * Av + DSu[0][L + 1] * Bv);
         }
       } else {
+        // path averages of the transverse shapes: (S0 + DS/2) and (S0/2 + DS/3)
+        // enter as S0_b (S0_c + DS_c/2) + DS_b (S0_c/2 + DS_c/3)
+        Real pa[3][NU], pb[3][NU];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int k = 0; k < NU; ++k) {
+            pa[d][k] = S0u[d][k] + half * DSu[d][k];
+            pb[d][k] = half * S0u[d][k] + third * DSu[d][k];
+          }
         // J1: prefix along x of DS_x * T_yz
 #pragma unroll
         for (int w = 0; w < NU; ++w) {
 #pragma unroll
           for (int v = 0; v < NU; ++v) {
             if ((v == L + 1 && !cross[1]) || (w == L + 1 && !cross[2])) continue;
-            const Real tr = S0u[1][v] * (S0u[2][w] + half * DSu[2][w]) +
-                            DSu[1][v] * (half * S0u[2][w] + third * DSu[2][w]);
-            const int ro = iu[0] + jwx * (iu[1] + v + jwy * (iu[2] + w));
+            const Real tr = S0u[1][v] * pa[2][w] + DSu[1][v] * pb[2][w];
+            const int ro = jpx * v + jpz * w;
             Real acc = Real(0);
 #pragma unroll
             for (int u = 0; u <= L; ++u) {
               acc += DSu[0][u] * tr;
-              if (u < L || cross[0]) sink(0, ro + u, kFix ? fma(kx, acc, ox) : kx * acc);
+              if (u < L || cross[0]) sink(0, jb + (ro + u), kFix ? fma(kx, acc, ox) : kx * acc);
             }
           }
         }
@@ -843,14 +862,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
           for (int u = 0; u < NU; ++u) {
             if ((u == L + 1 && !cross[0]) || (w == L + 1 && !cross[2])) continue;
-            const Real tr = S0u[0][u] * (S0u[2][w] + half * DSu[2][w]) +
-                            DSu[0][u] * (half * S0u[2][w] + third * DSu[2][w]);
-            const int co = iu[0] + u + jwx * (iu[1] + jwy * (iu[2] + w));
+            const Real tr = S0u[0][u] * pa[2][w] + DSu[0][u] * pb[2][w];
+            const int co = u + jpz * w;
             Real acc = Real(0);
 #pragma unroll
             for (int v = 0; v <= L; ++v) {
               acc += DSu[1][v] * tr;
-              if (v < L || cross[1]) sink(1, co + jwx * v, kFix ? fma(ky, acc, oy) : ky * acc);
+              if (v < L || cross[1]) sink(1, jb + (co + jpx * v), kFix ? fma(ky, acc, oy) : ky * acc);
             }
           }
         }
@@ -860,14 +878,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 #pragma unroll
           for (int u = 0; u < NU; ++u) {
             if ((u == L + 1 && !cross[0]) || (v == L + 1 && !cross[1])) continue;
-            const Real tr = S0u[0][u] * (S0u[1][v] + half * DSu[1][v]) +
-                            DSu[0][u] * (half * S0u[1][v] + third * DSu[1][v]);
-            const int co = iu[0] + u + jwx * (iu[1] + v + jwy * iu[2]);
+            const Real tr = S0u[0][u] * pa[1][v] + DSu[0][u] * pb[1][v];
+            const int co = u + jpx * v;
             Real acc = Real(0);
 #pragma unroll
             for (int w = 0; w <= L; ++w) {
               acc += DSu[2][w] * tr;
-              if (w < L || cross[2]) sink(2, co + jwx * jwy * w, kFix ? fma(kz, acc, oz) : kz * acc);
+              if (w < L || cross[2]) sink(2, jb + (co + jpz * w), kFix ? fma(kz, acc, oz) : kz * acc);
             }
           }
         }
@@ -990,7 +1007,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     const int gy = wrapi(org[1] + jo[1] + w1, R.n[1]);
     const int gz = (DIM == 3) ? wrapi(org[2] + jo[2] + w2, R.n[2]) : 0;
     const long long gi = gx + (long long)R.n[0] * (gy + (long long)R.n[1] * gz);
-    const int li = w0 + jwx * (w1 + jwy * w2);
+    const int li = w0 + jpx * w1 + jpz * w2;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       double v;
@@ -1051,7 +1068,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 // register block drops a wave and halves the workgroups a CU holds, which
 // costs far more than a few spilled values.  The 3D variant with the
 // partially skipped calculation is held to the plain kernel's three waves.
-template <class P, int L, int DIM, bool SKIP>
+template <class P, int L, int DIM, bool SKIP, int CP>
 __global__ void __launch_bounds__(gpd_block<DIM>())
 __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 4 : (SKIP ? 3 : 1))))
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
@@ -1077,33 +1094,39 @@ __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 4 : (SKIP ? 3 : 1))))
     }
     const int kt = runs[tile_run[g]].KT;
     if (kt == L + 1)
-      gpd_tile<P, L, DIM, L + 1, SKIP>(A, runs, tile_run, g, lds_dyn, sred, spc);
+      gpd_tile<P, L, DIM, L + 1, SKIP, CP>(A, runs, tile_run, g, lds_dyn, sred, spc);
     else
-      gpd_tile<P, L, DIM, L + 2, SKIP>(A, runs, tile_run, g, lds_dyn, sred, spc);
+      gpd_tile<P, L, DIM, L + 2, SKIP, CP>(A, runs, tile_run, g, lds_dyn, sred, spc);
     __syncthreads();
   }
 }
 
-template <class P, int L, int DIM>
-static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
+template <class P, int L, int DIM, bool SKIP, int CP>
+static hipError_t launch_variant(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
   const int grid = a.G < a.max_groups ? a.G : a.max_groups;
+  const void* k = reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, SKIP, CP>);
   if (lds > 64 * 1024) {
     // more than the default dynamic LDS of a launch (explicit large tiles)
-    const hipError_t e = a.skip ? hipFuncSetAttribute(reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, true>),
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                                : hipFuncSetAttribute(reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, false>),
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  // the variant with the partially skipped calculation only where a run uses
-  // it (its extra registers would cost the plain step occupancy)
-  if (a.skip)
-    hipLaunchKernelGGL((gpd_kernel<P, L, DIM, true>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs,
-                       a.tile_run);
-  else
-    hipLaunchKernelGGL((gpd_kernel<P, L, DIM, false>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs,
-                       a.tile_run);
+  hipLaunchKernelGGL((gpd_kernel<P, L, DIM, SKIP, CP>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs,
+                     a.tile_run);
   return hipGetLastError();
+}
+
+template <class P, int L, int DIM>
+static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
+  // the variant with the partially skipped calculation only where a run uses
+  // it (its extra registers would cost the plain step occupancy); 2D mixed
+  // precision windows of the constant row pitch take the variant compiled
+  // for it
+  if constexpr (DIM == 2 && !P::kAbs) {
+    if (a.fp[0] == kRowPitch2D && a.jp[0] == kRowPitch2D)
+      return a.skip ? launch_variant<P, L, DIM, true, kRowPitch2D>(a, lds, s)
+                    : launch_variant<P, L, DIM, false, kRowPitch2D>(a, lds, s);
+  }
+  return a.skip ? launch_variant<P, L, DIM, true, 0>(a, lds, s) : launch_variant<P, L, DIM, false, 0>(a, lds, s);
 }
 
 // Charge density of one run for the diagnostics, tile by tile (Eq.
@@ -1257,8 +1280,8 @@ hipError_t launch_rho_tiles(const GpdArgs<typename P::Real>& a, int run, int nti
 
 template <class P, int L, int DIM>
 static int occupancy_one(size_t lds, bool skip) {
-  const void* k = skip ? reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, true>)
-                       : reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, false>);
+  const void* k = skip ? reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, true, 0>)
+                       : reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, false, 0>);
   if (lds > 64 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int n = 0;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, gpd_block<DIM>(), lds);
