@@ -46,6 +46,25 @@ struct Pair<double> {
   using T = double2;
 };
 
+// A move by step (|step| < 1 cell) from in-cell offset f in [0, 1): the new
+// offset t and the cell change dc in {-1, 0, 1}.  f + step lies in (-1, 2);
+// its floor is dc and the remainder t (exact for f + step >= 0, one rounding
+// below).  Just below the lower face that rounding can give t = 1: the
+// particle then stays on the face of its old cell (t = 0, dc = 0).
+template <class Real>
+__device__ __forceinline__ void cell_step(Real f, Real step, Real& t, int& dc) {
+  const Real x = f + step;
+  const Real fl = floor(x);
+  const Real r = x - fl;
+  const bool up = r >= Real(1);
+  t = up ? Real(0) : r;
+  dc = up ? 0 : (int)fl;
+}
+
+// Product of two integers of magnitude below 2^23 (window indices, pitches
+// and their products within a window) on the full-rate 24-bit multiplier;
+// a 32-bit multiply by a variable issues at a quarter of the rate.
+__device__ __forceinline__ int imul24(int a, int b) { return __mul24(a, b); }
 
 // Sum over a 3D stencil of a staged component: weights along x, y, z are wx
 // (NX nodes), wy (NY), wz (NZ); ox, oy, oz the window index of the first node;
@@ -54,12 +73,13 @@ template <int NX, int NY, int NZ, class Real>
 __device__ __forceinline__ Real gather3(const Real* Fc, int px, int pz, const Real* wx, const Real* wy,
                                         const Real* wz, int ox, int oy, int oz) {
   Real s = Real(0);
+  const Real* base = Fc + (ox + imul24(px, oy) + imul24(pz, oz));
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
     Real sy = Real(0);
 #pragma unroll
     for (int j = 0; j < NY; ++j) {
-      const Real* row = Fc + ox + px * (oy + j) + pz * (oz + k);
+      const Real* row = base + (px * j + pz * k);
       Real sx = Real(0);
 #pragma unroll
       for (int i = 0; i < NX; ++i) sx += wx[i] * row[i];
@@ -98,6 +118,30 @@ __device__ __forceinline__ void lds_addq(int* p, double v) {
 __device__ __forceinline__ int in_vgpr(int x) {
   asm volatile("" : "+v"(x));
   return x;
+}
+
+// Element of a particle array at a byte offset from its base.  The particle
+// loop addresses a tile's arrays from the tile's first particle with one
+// 32-bit offset that the compiler cannot rewrite into per-array pointers:
+// every access is then a scalar base plus that vector offset, one add per
+// particle, instead of a 64-bit pointer per array advanced every iteration
+// in vector registers.
+template <class T>
+__device__ __forceinline__ T& at(T* base, unsigned off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+// (A block that stores through an offset computed in another block takes it
+// through fresh_off first: the address then forms in the storing block, where
+// it can still be split into the scalar base and the vector offset.)
+template <class Real>
+__device__ __forceinline__ unsigned part_off(int q) {
+  unsigned o = (unsigned)q * (unsigned)sizeof(Real);
+  asm volatile("" : "+v"(o));
+  return o;
+}
+__device__ __forceinline__ unsigned fresh_off(unsigned o) {
+  asm volatile("" : "+v"(o));
+  return o;
 }
 
 // m mod n for -n <= m < n, without an integer division or a compare: the
@@ -222,6 +266,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     fits = fits && fs[d] >= 1 && jsz[d] >= 1 && fs[d] <= A.fw[d] && jsz[d] <= A.jw[d];
   }
   const int sA = A.seg[2 * g], sB = A.seg[2 * g + 1], sC = A.seg[2 * g + 2];
+  // byte offsets within the tile are 32-bit
+  fits = fits && (unsigned)(sC - sA) <= 0xffffffffu / (unsigned)sizeof(Real);
   if (!fits) {
     // cannot happen while the re-sort guard holds; report and leave the tile
     if (tid == 0) {
@@ -388,7 +434,14 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   if (tid >= 6 && tid < 13) sred[tid] = 0;
   __syncthreads();
 
-  const PBuf<Real> B = A.buf[A.st->parity];
+  // the tile's particles, from its first one (offsets from part_off)
+  PBuf<Real> B = A.buf[A.st->parity];
+  B.cell += sA;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    B.pos[d] += sA;
+    B.u[d] += sA;
+  }
   int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
   int nbad = 0, noor = 0;
   const Real third = Real(1) / Real(3);
@@ -422,7 +475,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // velocity (the arithmetic of the move in the loop below) and deposits no
   // current; it still counts for the box, the cell counts and the next
   // step's fixed-point bounds
-  auto drift = [&](int p, const int* c, const Real* f, const Real* xo, Real u0, Real u1, Real u2, const int* rel) {
+  auto drift = [&](unsigned o_in, const int* c, const Real* f, const Real* xo, Real u0, Real u1, Real u2, const int* rel) {
+    const unsigned o = fresh_off(o_in);
     const Real ig = fast_rsqrt(Real(1) + u0 * u0 + u1 * u1 + u2 * u2);
     const Real vd[3] = {u0 * ig, u1 * ig, u2 * ig};
     int cwi = 0, cw[3] = {0, 0, 0};
@@ -439,24 +493,14 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         const Real nd = Real(R.n[d]);
         while (w < Real(0)) w += nd;
         while (w >= nd) w -= nd;
-        B.pos[d][p] = w;
+        at(B.pos[d], o) = w;
       } else {
-        Real t = f[d] + step;
-        int dc = 0;
-        if (t >= Real(1)) {
-          t -= Real(1);
-          dc = 1;
-        } else if (t < Real(0)) {
-          t += Real(1);
-          dc = -1;
-          if (t >= Real(1)) {
-            t = Real(0);
-            dc = 0;
-          }
-        }
+        Real t;
+        int dc;
+        cell_step(f[d], step, t, dc);
         cnd = c[d] + dc;
         ddd = (t - f[d]) + Real(dc);
-        B.pos[d][p] = t;
+        at(B.pos[d], o) = t;
         int m = cnd;
         if (m < 0) m += R.n[d];
         else if (m >= R.n[d]) m -= R.n[d];
@@ -467,11 +511,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       const int rn = rel[d] + (cnd - c[d]);
       bmin[d] = min(bmin[d], rn);
       bmax[d] = max(bmax[d], rn);
-      cwi += (rn - jo_[d]) * jws[d];
+      cwi += imul24(rn - jo_[d], jws[d]);
     }
     if (kFix && DIM == 2) mnew[2] = max(mnew[2], __float_as_int((float)fabs(vd[2])));
     if (kCnt) atomicAdd(Cw + cwi, 1);
-    if (!P::kAbs) B.cell[p] = pack_cell<DIM>(cw[0], cw[1], cw[2]);
+    if (!P::kAbs) at(B.cell, o) = pack_cell<DIM>(cw[0], cw[1], cw[2]);
   };
   if (SKIP && smode == 1) {
     // every particle of the tile drifts: several particles per thread with
@@ -482,21 +526,21 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       Real ff[U][3], xx[U][3], uu[U][3];
 #pragma unroll
       for (int k = 0; k < U; ++k) {
-        const int p = min(p0 + k * nth, sC - 1);
+        const unsigned o = part_off<Real>(min(p0 + k * nth, sC - 1) - sA);
         cc[k][0] = cc[k][1] = cc[k][2] = 0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) ff[k][d] = xx[k][d] = Real(0);
         if (P::kAbs) {
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) xx[k][d] = B.pos[d][p];
+          for (int d = 0; d < DIM; ++d) xx[k][d] = at(B.pos[d], o);
         } else {
-          unpack_cell<DIM>(B.cell[p], cc[k][0], cc[k][1], cc[k][2]);
+          unpack_cell<DIM>(at(B.cell, o), cc[k][0], cc[k][1], cc[k][2]);
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) ff[k][d] = B.pos[d][p];
+          for (int d = 0; d < DIM; ++d) ff[k][d] = at(B.pos[d], o);
         }
-        uu[k][0] = B.u[0][p];
-        uu[k][1] = B.u[1][p];
-        uu[k][2] = B.u[2][p];
+        uu[k][0] = at(B.u[0], o);
+        uu[k][1] = at(B.u[1], o);
+        uu[k][2] = at(B.u[2], o);
       }
 #pragma unroll
       for (int k = 0; k < U; ++k) {
@@ -522,13 +566,14 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
           ++noor;
           continue;
         }
-        drift(p, cc[k], ff[k], xx[k], uu[k][0], uu[k][1], uu[k][2], rel);
+        drift(part_off<Real>(p - sA), cc[k], ff[k], xx[k], uu[k][0], uu[k][1], uu[k][2], rel);
       }
     }
   }
 
   for (int p = (SKIP && smode == 1) ? sC : sA + tid; p < sC; p += nth) {
     const int sp = (p >= sB) ? 1 : 0;
+    const unsigned o = part_off<Real>(p - sA);
     // ---- load ---------------------------------------------------------
     int c[3] = {0, 0, 0};
     Real f[3] = {Real(0), Real(0), Real(0)};
@@ -536,17 +581,17 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     if (P::kAbs) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        xo[d] = B.pos[d][p];
+        xo[d] = at(B.pos[d], o);
         const Real fl = floor(xo[d]);
         c[d] = (int)fl;
         f[d] = xo[d] - fl;
       }
     } else {
-      unpack_cell<DIM>(B.cell[p], c[0], c[1], c[2]);
+      unpack_cell<DIM>(at(B.cell, o), c[0], c[1], c[2]);
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) f[d] = B.pos[d][p];
+      for (int d = 0; d < DIM; ++d) f[d] = at(B.pos[d], o);
     }
-    Real u0 = B.u[0][p], u1 = B.u[1][p], u2 = B.u[2][p];
+    Real u0 = at(B.u[0], o), u1 = at(B.u[1], o), u2 = at(B.u[2], o);
     // all six loads are in flight before anything waits on one of them (left
     // alone, the compiler sinks the offset and momentum loads below the
     // window test, a second memory round trip per particle)
@@ -575,7 +620,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         drifting = !skip_perturbed<DIM>(R, xa, ct);
       }
       if (drifting) {
-        drift(p, c, f, xo, u0, u1, u2, rel);
+        drift(o, c, f, xo, u0, u1, u2, rel);
         continue;
       }
     }
@@ -606,11 +651,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     // ---- gather ------------------------------------------------------------
     Real E0, E1, E2, B0, B1, B2;
     if (DIM == 2) {
+      const int rt = imul24(fpx, it[1]), rh = imul24(fpx, ih[1]);
       // (E1, B2): W along x (half lattice), T along y
       E0 = B1 = Real(0);
 #pragma unroll
       for (int j = 0; j < KT; ++j) {
-        const Real2* row = P1 + ih[0] + fpx * (it[1] + j);
+        const Real2* row = P1 + (ih[0] + rt) + fpx * j;
         Real se = Real(0), sb = Real(0);
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
@@ -625,7 +671,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       E1 = B0 = Real(0);
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        const Real2* row = P2 + it[0] + fpx * (ih[1] + j);
+        const Real2* row = P2 + (it[0] + rh) + fpx * j;
         Real se = Real(0), sb = Real(0);
 #pragma unroll
         for (int i = 0; i < KT; ++i) {
@@ -669,7 +715,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int d = 0; d < DIM; ++d) {
         bmin[d] = min(bmin[d], rel[d]);
         bmax[d] = max(bmax[d], rel[d]);
-        cwi += (rel[d] - jo_[d]) * jws[d];
+        cwi += imul24(rel[d] - jo_[d], jws[d]);
       }
       if (kCnt) atomicAdd(Cw + cwi, 1);
       continue;
@@ -699,19 +745,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         while (w >= nd) w -= nd;
         xw[d] = w;
       } else {
-        Real t = f[d] + step;
-        int dc = 0;
-        if (t >= Real(1)) {
-          t -= Real(1);
-          dc = 1;
-        } else if (t < Real(0)) {
-          t += Real(1);
-          dc = -1;
-          if (t >= Real(1)) {
-            t = Real(0);
-            dc = 0;
-          }
-        }
+        Real t;
+        int dc;
+        cell_step(f[d], step, t, dc);
         fn[d] = t;
         cn[d] = c[d] + dc;
         dd[d] = (t - f[d]) + Real(dc);
@@ -727,46 +763,60 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       Real g0, g1;
       tab_split(Tw, c[d], f[d], b0, g0);
       tab_split(Tw, cn[d], fn[d], b1, g1);
-      Real s0[NW], dA[NW], dB[NW];
+      Real s0[NW], s1[NW], dA[NW], dB[NW], a0[NU], ds[NU];
       tab_eval<L, NW, false>(Tw, g0, s0);
       const int db = b1 - b0;
       cross[d] = db != 0;
       const bool shA = db < 0, shB = db > 0;
+      iu[d] = rel[d] + (min(b0, b1) - c[d]) + uoff[d];
+      // Node k of the union is node k of S0 unless the new stencil starts one
+      // node lower (shA), then node k - 1.  A wave whose steps are all short
+      // and none of which changed its stencil takes the cheapest form.
       if (__all(fabs(dd[d]) >= Real(0.0625))) {
         // every step of the wave is long: S1 - S0 directly keeps its
         // precision (rounding of order one against |step| >= 1/16)
-        Real s1[NW];
         tab_eval<L, NW, false>(Tw, g1, s1);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
-          const Real a0 = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));
+          a0[k] = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));
           const Real a1 = shB ? (k >= 1 ? s1[k - 1] : Real(0)) : (k < NW ? s1[k] : Real(0));
-          S0u[d][k] = a0;
-          DSu[d][k] = a1 - a0;
+          ds[k] = a1 - a0[k];
         }
-        iu[d] = rel[d] + (min(b0, b1) - c[d]) + uoff[d];
-        return;
-      }
-      const Real eA = (db == 0) ? g1 : (db > 0 ? Real(1) : Real(0));
-      const Real lA = (db == 0) ? dd[d] : (db > 0 ? Real(1) - g0 : -g0);
-      tab_diff<L>(Tw, g0, eA, lA, dA);
-      if (db != 0) {
-        const Real sBv = (db > 0) ? Real(0) : Real(1);
-        const Real lB = (db > 0) ? g1 : g1 - Real(1);
-        tab_diff<L>(Tw, sBv, g1, lB, dB);
-      } else {
+      } else if (!__any(db != 0)) {
+        // no lane of the wave changed its stencil: one divided difference
+        tab_diff<L, kFix>(Tw, g0, g1, dd[d], dA);
 #pragma unroll
-        for (int k = 0; k < NW; ++k) dB[k] = Real(0);
+        for (int k = 0; k < NU; ++k) {
+          a0[k] = k < NW ? s0[k] : Real(0);
+          ds[k] = k < NW ? dA[k] : Real(0);
+        }
+      } else {
+        // a stencil that moved splits its difference at the lattice point
+        // it crossed (an end of g's range)
+        const Real eA = (db == 0) ? g1 : (db > 0 ? Real(1) : Real(0));
+        const Real lA = (db == 0) ? dd[d] : (db > 0 ? Real(1) - g0 : -g0);
+        tab_diff<L, kFix>(Tw, g0, eA, lA, dA);
+        if (db != 0) {
+          const Real sBv = (db > 0) ? Real(0) : Real(1);
+          const Real lB = (db > 0) ? g1 : g1 - Real(1);
+          tab_diff<L, kFix>(Tw, sBv, g1, lB, dB);
+        } else {
+#pragma unroll
+          for (int k = 0; k < NW; ++k) dB[k] = Real(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+          a0[k] = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));
+          const Real da = shA ? (k >= 1 ? dA[k - 1] : Real(0)) : (k < NW ? dA[k] : Real(0));
+          const Real dbv = shB ? (k >= 1 ? dB[k - 1] : Real(0)) : (k < NW ? dB[k] : Real(0));
+          ds[k] = da + dbv;
+        }
       }
 #pragma unroll
       for (int k = 0; k < NU; ++k) {
-        const Real a0 = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));
-        const Real da = shA ? (k >= 1 ? dA[k - 1] : Real(0)) : (k < NW ? dA[k] : Real(0));
-        const Real dbv = shB ? (k >= 1 ? dB[k - 1] : Real(0)) : (k < NW ? dB[k] : Real(0));
-        S0u[d][k] = a0;
-        DSu[d][k] = da + dbv;
+        S0u[d][k] = a0[k];
+        DSu[d][k] = ds[k];
       }
-      iu[d] = rel[d] + (min(b0, b1) - c[d]) + uoff[d];
     };
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -785,7 +835,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     // pitch is a compile-time constant), so a row costs one add at most.
     auto deposit = [&](auto sink, const Real kx, const Real ky, const Real kz, const Real ox, const Real oy,
                        const Real oz) {
-      const int jb = iu[0] + jpx * iu[1] + (DIM == 3 ? jpz * iu[2] : 0);
+      const int jb = iu[0] + imul24(jpx, iu[1]) + (DIM == 3 ? imul24(jpz, iu[2]) : 0);
       if (DIM == 2) {
         // Slot L+1 of an axis (and the last prefix face along it) is nonzero
         // only when the particle's stencil widened along that axis.
@@ -929,12 +979,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       const int rn = rel[d] + (cn[d] - c[d]);
       bmin[d] = min(bmin[d], rn);
       bmax[d] = max(bmax[d], rn);
-      cwi += (rn - jo_[d]) * jws[d];
+      cwi += imul24(rn - jo_[d], jws[d]);
     }
     if (kCnt) atomicAdd(Cw + cwi, 1);
+    const unsigned os = fresh_off(o);
     if (P::kAbs) {
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) B.pos[d][p] = xw[d];
+      for (int d = 0; d < DIM; ++d) at(B.pos[d], os) = xw[d];
     } else {
       int cw[3] = {0, 0, 0};
 #pragma unroll
@@ -943,13 +994,13 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         if (m < 0) m += R.n[d];
         else if (m >= R.n[d]) m -= R.n[d];
         cw[d] = m;
-        B.pos[d][p] = fn[d];
+        at(B.pos[d], os) = fn[d];
       }
-      B.cell[p] = pack_cell<DIM>(cw[0], cw[1], cw[2]);
+      at(B.cell, os) = pack_cell<DIM>(cw[0], cw[1], cw[2]);
     }
-    B.u[0][p] = u0;
-    B.u[1][p] = u1;
-    B.u[2][p] = u2;
+    at(B.u[0], os) = u0;
+    at(B.u[1], os) = u1;
+    at(B.u[2], os) = u2;
   }
 
   // ---- box and counters: wave reduction, then one LDS atomic per wave ------

@@ -73,7 +73,9 @@ __host__ __device__ inline void tab_eval(const Tab<Real>& t, Real g, Real* w) {
 // Weight differences w_k(e) - w_k(g) = (e - g) * sum_{r>=1} c[k][r] h_r(g, e),
 // h_r = sum_{i+j=r-1} g^i e^j, written as d * (divided difference) so that a
 // short step d = e - g keeps full relative precision.  Knot-free tables only.
-template <int L, class Real>
+// CONST: the table is a compile-time constant, whose zero coefficients are
+// left out (a product with a zero the compiler must otherwise keep).
+template <int L, bool CONST = false, class Real>
 __host__ __device__ inline void tab_diff(const Tab<Real>& t, Real g, Real e, Real d, Real* dw) {
   Real h[kMaxCoef];
   h[1] = Real(1);
@@ -87,7 +89,8 @@ __host__ __device__ inline void tab_diff(const Tab<Real>& t, Real g, Real e, Rea
   for (int k = 0; k <= L; ++k) {
     Real acc = t.c[k][L] * h[L];
 #pragma unroll
-    for (int r = L - 1; r >= 1; --r) acc += t.c[k][r] * h[r];
+    for (int r = L - 1; r >= 1; --r)
+      if (!CONST || t.c[k][r] != Real(0)) acc += t.c[k][r] * h[r];
     dw[k] = d * acc;
   }
 }
