@@ -19,8 +19,9 @@ repetitions; inputs resident in HBM); `fp64` holds the same figures for the
 FP64 path, measured in the same run.  `roofline` refers to the dominant
 kernel, the gather-push-deposit kernel: its average launch time comes from
 HIP events on the context stream around a graph holding that kernel alone,
-replayed once per step of K further steps (pic_kernel_timing; the sort checks
-and the field update run between the replays), and `achieved` is its algorithmic
+replayed once per step of K further steps after W discarded ones
+(pic_kernel_timing; the sort checks and the field update run between the
+replays), and `achieved` is its algorithmic
 bytes per launch (particle state read and written once, E and B read and J
 written once per cell) over that time.  `traffic` is the HBM traffic per
 launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters stored under profiles/
@@ -366,7 +367,11 @@ def run_leg(args, specs, species, prec_name, check_runs):
         ms_graph = float(np.median(graph_ms))
 
         # the particle kernel's own time: K more steps, each replaying a graph
-        # of the particle kernel alone between two stream events
+        # of the particle kernel alone between two stream events, after W
+        # steps in the same mode whose times are discarded (the first launches
+        # of the switched mode run slower)
+        wt.pic_kernel_timing(sim.ctx, True)
+        sim.step(max(args.warmup, 3))
         wt.pic_kernel_timing(sim.ctx, True)
         sim.step(args.steps)
         gpd_ms, launches = wt.pic_kernel_timing(sim.ctx, False)

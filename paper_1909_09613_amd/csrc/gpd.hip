@@ -119,6 +119,24 @@ __device__ __forceinline__ int in_vgpr(int x) {
   asm volatile("" : "+v"(x));
   return x;
 }
+__device__ __forceinline__ float in_vgpr(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Split of a position for a table known only at run time (T_l): with
+// d = f - sigma in (-1, 1), g = fract(d) and base = cell - (d < 0), one
+// fract where a select between two run-time constants takes three
+// instructions.  (fract returns d + 1 for d < 0, clamped below 1, and d
+// itself when the table has no split, sigma = 0.)
+__device__ __forceinline__ float fract_(float x) { return __builtin_amdgcn_fractf(x); }
+__device__ __forceinline__ double fract_(double x) { return __builtin_amdgcn_fract(x); }
+template <class Real>
+__device__ __forceinline__ void split_rt(const Tab<Real>& t, int cell, Real f, int& base, Real& g) {
+  const Real d = f - t.sigma;
+  base = cell - (d < Real(0) ? 1 : 0);
+  g = fract_(d);
+}
 
 // Element of a particle array at a byte offset from its base.  The particle
 // loop addresses a tile's arrays from the tile's first particle with one
@@ -434,6 +452,15 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   if (tid >= 6 && tid < 13) sred[tid] = 0;
   __syncthreads();
 
+  // 2D FP32: the leading coefficients of the T_l tables in vector registers,
+  // so that the first Horner step of each node reads one scalar operand (an
+  // instruction reads at most one) and needs no copy
+  Real ttop[2][KT];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int k = 0; k < KT; ++k) ttop[d][k] = (kFix && DIM == 2) ? in_vgpr(float(R.T[d].c[k][L])) : Real(0);
+
   // the tile's particles, from its first one (offsets from part_off)
   PBuf<Real> B = A.buf[A.st->parity];
   B.cell += sA;
@@ -643,8 +670,8 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       else weights_h(d, R.Wh[d]);
       int b;
       Real gg;
-      tab_split(R.T[d], c[d], f[d], b, gg);
-      tab_eval<L, KT, true>(R.T[d], gg, wt[d]);
+      split_rt(R.T[d], c[d], f[d], b, gg);
+      tab_eval<L, KT, true>(R.T[d], gg, wt[d], (kFix && DIM == 2) ? ttop[d] : nullptr);
       it[d] = rel[d] + (b - c[d]) + toff[d];
     }
 

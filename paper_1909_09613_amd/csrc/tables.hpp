@@ -52,8 +52,10 @@ __host__ __device__ inline Real ipow(Real x, int l) {
 }
 
 // Weights w[0..K-1] at in-frame coordinate g (L = order, K = node count).
+// top, if given, holds the leading coefficients c[k][L] (a copy the caller
+// keeps elsewhere, e.g. in registers).
 template <int L, int K, bool KNOT, class Real>
-__host__ __device__ inline void tab_eval(const Tab<Real>& t, Real g, Real* w) {
+__host__ __device__ inline void tab_eval(const Tab<Real>& t, Real g, Real* w, const Real* top = nullptr) {
   Real tk = 0;
   if (KNOT) {
     Real d = g - t.kappa;
@@ -62,7 +64,7 @@ __host__ __device__ inline void tab_eval(const Tab<Real>& t, Real g, Real* w) {
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    Real acc = t.c[k][L];
+    Real acc = top ? top[k] : t.c[k][L];
 #pragma unroll
     for (int r = L - 1; r >= 0; --r) acc = acc * g + t.c[k][r];
     if (KNOT) acc += t.alpha[k] * tk;
