@@ -46,11 +46,16 @@ __host__ __device__ inline void unpack_cell(int c, int& x, int& y, int& z) {
   }
 }
 
-// Row pitch (elements) of the 2D mixed-precision field and current windows
-// whenever they are at most this wide: a compile-time pitch turns the rows of
-// a particle's stencil into immediate LDS offsets, and 48 measured fastest
-// for the 32 x 16 tile's 41- and 42-node rows.
-constexpr int kRowPitch2D = 48;
+// Row pitches (elements) of the 2D mixed-precision field and current windows
+// whenever they are at most this wide.  A compile-time pitch turns the rows of
+// a particle's stencil into immediate LDS offsets.  The LDS serves a wave's
+// 4-byte reads 32 lanes (one row of the wave's cells) at a time over 32
+// banks; the lanes whose T_l or W_l stencil starts one row lower read the
+// row above, which with a pitch of 64 (a multiple of 32) falls on other
+// banks than the rest of the half-wave's reads.  Current atomics showed no
+// such dependence, and their windows keep the smaller pitch 48.
+constexpr int kFieldPitch2D = 64;
+constexpr int kCurrentPitch2D = 48;
 
 // Per-run constants, one entry per run in device memory.
 template <class Real>

@@ -324,11 +324,12 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // windows: index x + row pitch * y + plane pitch * z (the pitches may
   // exceed the extents, so that the rows a wave reads at once spread over
   // the LDS banks)
-  // (CP > 0: the row pitch is that compile-time constant, so that the rows
-  // of a stencil are immediate offsets from one address)
+  // (CP > 0: the field row pitch is that compile-time constant and the
+  // current row pitch kCurrentPitch2D, so that the rows of a stencil are
+  // immediate offsets from one address)
   const int fpx = CP > 0 ? CP : A.fp[0], fpz = A.fp[1];
   const int fcap = (DIM == 3) ? fpz * A.fw[2] : fpx * A.fw[1];
-  const int jpx = CP > 0 ? CP : A.jp[0], jpz = A.jp[1];
+  const int jpx = CP > 0 ? kCurrentPitch2D : A.jp[0], jpz = A.jp[1];
   const int jcap = (DIM == 3) ? jpz * A.jw[2] : jpx * A.jw[1];
   const long long NT = A.ncell_total;
   const Real* Fg = A.F + R.cell0;
@@ -1200,9 +1201,9 @@ static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hip
   // precision windows of the constant row pitch take the variant compiled
   // for it
   if constexpr (DIM == 2 && !P::kAbs) {
-    if (a.fp[0] == kRowPitch2D && a.jp[0] == kRowPitch2D)
-      return a.skip ? launch_variant<P, L, DIM, true, kRowPitch2D>(a, lds, s)
-                    : launch_variant<P, L, DIM, false, kRowPitch2D>(a, lds, s);
+    if (a.fp[0] == kFieldPitch2D && a.jp[0] == kCurrentPitch2D)
+      return a.skip ? launch_variant<P, L, DIM, true, kFieldPitch2D>(a, lds, s)
+                    : launch_variant<P, L, DIM, false, kFieldPitch2D>(a, lds, s);
   }
   return a.skip ? launch_variant<P, L, DIM, true, 0>(a, lds, s) : launch_variant<P, L, DIM, false, 0>(a, lds, s);
 }
