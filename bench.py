@@ -415,7 +415,9 @@ def run_leg(args, specs, species, prec_name, check_runs):
             peak = CUS * CLOCK_GHZ * 1e9
             valu = {"insts_per_launch": ctr["valu_insts_per_launch"], "achieved": rate, "peak": peak,
                     "unit": "wave-instructions/s", "frac": rate / peak,
-                    "per_particle": ctr["valu_insts_per_launch"] * 64.0 / np_total}
+                    # a wave-instruction serves 64 particles, one per lane: this is
+                    # the count of vector instructions each particle goes through
+                    "per_particle_lane": ctr["valu_insts_per_launch"] * 64.0 / np_total}
     out.update({
         "value": np_total * args.steps / (ms_graph / 1e3),
         "ms_per_step": ms_step,
