@@ -167,11 +167,27 @@ __device__ __forceinline__ unsigned fresh_off(unsigned o) {
 // reduced to [0, n), differ by less than n.
 __device__ __forceinline__ int wrap_once(int m, int n) { return m + (n & (m >> 31)); }
 
-// 1 / sqrt(x) and 1 / x: hardware approximations (1 ulp) for FP32, IEEE for FP64.
+// 1 / sqrt(x) and 1 / x for x >= 1 (1 + |u|^2, 1 + |t|^2).  FP32: the
+// hardware approximations (1 ulp).  FP64: the hardware estimates (about 23
+// correct bits) refined by two Newton steps, each of which doubles the
+// correct bits, to within a few ulp (the IEEE square root and division
+// take about 20 instructions each; 7 and 5 here).  An infinite argument (a
+// diverged particle) gives NaN, which the push reports as non-finite.
 __device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double fast_rsqrt(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-h * y, y, 1.5);  // y (3 - x y^2) / 2
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double fast_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);  // y (2 - x y)
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
 
 // ---- partially skipped calculation (Sec. 3) ---------------------------------
 // A particle at canonical position x (cell units, [0, n) per axis) lies in

@@ -2,7 +2,7 @@
 candidate list, leaves the simulation state exactly as it found it (the trial
 steps are undone), and the steps taken afterwards with the chosen tiling match
 those of a context that keeps the default tiling (the tiling changes only the
-order in which current contributions are summed).
+order in which current contributions are summed) and those of the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -36,7 +36,7 @@ def _state(sim, spec):
 
 @pytest.mark.parametrize("spec,precision", CASES,
                          ids=["%dd-%s" % (c.ndim, "fp64" if p == wt.PIC_FP64 else "mixed32") for c, p in CASES])
-def test_autotune_restores_state_and_steps_like_default(spec, precision):
+def test_autotune_restores_state_and_steps_like_default(orc, spec, precision):
     fp32 = precision == wt.PIC_MIXED32
     sp, E, B = H.random_state(spec, 5, amp=0.05, fp32=fp32)
     a = wt.Sim([spec], precision)
@@ -73,6 +73,20 @@ def test_autotune_restores_state_and_steps_like_default(spec, precision):
     finally:
         a.close()
         b.close()
+    # the autotuned context against the oracle over the same six steps
+    g = H.oracle_grid(orc, spec)
+    g.E[:] = E
+    g.B[:] = B
+    oref = H.copy_species(sp)
+    for _ in range(6):
+        g.step(oref)
+    ox, ou = H.particle_errors(spec, oref, xa)
+    oE, oB = max(H.rel_maxnorm(Ea, g.E)), max(H.rel_maxnorm(Ba, g.B))
+    print("autotuned vs oracle after 6 steps: dx=%.2e du=%.2e dE=%.2e dB=%.2e" % (ox, ou, oE, oB), flush=True)
+    if fp32:
+        assert ox <= 1e-4 and ou <= 1e-4 and oE <= 1e-3 and oB <= 1e-3
+    else:
+        assert ox <= 1e-12 and ou <= 1e-12 and oE <= 1e-11 and oB <= 1e-11
     ref = [{"x": x, "u": u} for x, u in xb]
     ex, eu = H.particle_errors(spec, ref, xa)
     print("autotuned vs default after 6 steps: dx=%.2e du=%.2e" % (ex, eu), flush=True)
