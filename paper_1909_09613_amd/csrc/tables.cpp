@@ -55,37 +55,23 @@ bool build_table(int l, int kind, double a_in, Tab<double>& out, const char** er
   long double fact = 1.0L;
   for (int i = 2; i <= l; ++i) fact *= i;
 
+  // T_l on the integer lattice: a sum of truncated powers beta (y - t)_+^l
   long double beta[16], t[16];
   int nterms = 0;
-  long double lam, sigma, first_f;
-  int K;
-  if (kind <= 1) {
-    lam = (kind == 0) ? 0.5L : 0.0L;
-    sigma = frac(lam - 0.5L * (l + 1));
-    first_f = sigma - lam - 0.5L * (l - 1);
-    K = l + 1;
-    for (int j = 0; j <= l + 1; ++j) {
-      beta[nterms] = ((j & 1) ? -1.0L : 1.0L) * binom(l + 1, j) / fact;
-      t[nterms] = j - 0.5L * (l + 1);
-      ++nterms;
-    }
-  } else {
-    lam = 0.0L;
-    sigma = frac(0.5L * l + a);
-    first_f = sigma - 0.5L * l - a + 1.0L;
-    K = (a_in <= 0.5) ? l + 1 : l + 2;
-    for (int j = 0; j <= l; ++j) {
-      long double b = ((j & 1) ? -1.0L : 1.0L) * binom(l, j) / (2.0L * a * fact);
-      beta[nterms] = b;
-      t[nterms] = j - 0.5L * l - a;
-      ++nterms;
-      beta[nterms] = -b;
-      t[nterms] = j - 0.5L * l + a;
-      ++nterms;
-    }
+  const long double sigma = frac(0.5L * l + a);
+  const long double first_f = sigma - 0.5L * l - a + 1.0L;
+  const int K = (a_in <= 0.5) ? l + 1 : l + 2;
+  for (int j = 0; j <= l; ++j) {
+    long double b = ((j & 1) ? -1.0L : 1.0L) * binom(l, j) / (2.0L * a * fact);
+    beta[nterms] = b;
+    t[nterms] = j - 0.5L * l - a;
+    ++nterms;
+    beta[nterms] = -b;
+    t[nterms] = j - 0.5L * l + a;
+    ++nterms;
   }
   const int first = (int)lroundl(first_f);
-  const long double D = sigma - first - lam;  // y = g + D - k for node k
+  const long double D = sigma - first;  // y = g + D - k for node k
 
   long double c[kMaxNodes][kMaxCoef] = {};
   long double alpha[kMaxNodes] = {};

@@ -83,10 +83,12 @@ def test_autotune_restores_state_and_steps_like_default(orc, spec, precision):
     ox, ou = H.particle_errors(spec, oref, xa)
     oE, oB = max(H.rel_maxnorm(Ea, g.E)), max(H.rel_maxnorm(Ba, g.B))
     print("autotuned vs oracle after 6 steps: dx=%.2e du=%.2e dE=%.2e dB=%.2e" % (ox, ou, oE, oB), flush=True)
+    # mixed precision: ~2e-6 per step of FP32 rounding over six steps; FP64:
+    # the benchmark spec's bound (measured 1e-14 and below)
     if fp32:
-        assert ox <= 1e-4 and ou <= 1e-4 and oE <= 1e-3 and oB <= 1e-3
+        assert ox <= 1e-5 and ou <= 1e-5 and oE <= 1e-4 and oB <= 1e-4
     else:
-        assert ox <= 1e-12 and ou <= 1e-12 and oE <= 1e-11 and oB <= 1e-11
+        assert ox <= 1e-12 and ou <= 1e-12 and oE <= 1e-12 and oB <= 1e-12
     ref = [{"x": x, "u": u} for x, u in xb]
     ex, eu = H.particle_errors(spec, ref, xa)
     print("autotuned vs default after 6 steps: dx=%.2e du=%.2e" % (ex, eu), flush=True)
