@@ -61,6 +61,14 @@ __device__ __forceinline__ void cell_step(Real f, Real step, Real& t, int& dc) {
   dc = up ? 0 : (int)fl;
 }
 
+// The periodic image in [0, n) of a cell m = c + dc reached by a step dc in
+// {-1, 0, 1} from c in [0, n): m is then -1, n or already in range.  One
+// unsigned compare (-1 is out of range too), and the sign bit of m selects
+// n - 1 or 0.
+__device__ __forceinline__ int wrap_step(int m, int n) {
+  return ((unsigned)m >= (unsigned)n) ? ((m >> 31) & (n - 1)) : m;
+}
+
 // Product of two integers of magnitude below 2^23 (window indices, pitches
 // and their products within a window) on the full-rate 24-bit multiplier;
 // a 32-bit multiply by a variable issues at a quarter of the rate.
@@ -496,7 +504,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // (kept in vector registers on the FP32 path, where scalar registers run
   // out; the FP64 path needs its vector registers for its own state)
   auto pin = [](int x) { return P::kAbs ? x : in_vgpr(x); };
-  int co[3], lo_[3], nn[3], rlo[3], rhi[3], hoff[3], toff[3], uoff[3], jo_[3], jws[3];
+  int co[3], lo_[3], nn[3], rlo[3], rhi[3], hoff[3], toff[3], uoff[3], jo_[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int n = R.n[d];
@@ -511,8 +519,10 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
     toff[d] = pin(R.T[d].first - fo[d]);
     uoff[d] = pin(R.Wi[d].first - jo[d]);
     jo_[d] = pin(jo[d]);
-    jws[d] = pin(d == 0 ? 1 : (d == 1 ? jpx : jpz));
   }
+  // offset along axis d in the current and count windows (their row and
+  // plane pitch; compile-time constants in the 2D variant with fixed pitches)
+  auto cwin = [&](int d, int r) { return d == 0 ? r : imul24(r, d == 1 ? jpx : jpz); };
 
   // partially skipped calculation: outside the perturbed region a particle
   // follows pure drift -- it keeps its momentum, moves with that momentum's
@@ -545,17 +555,14 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         cnd = c[d] + dc;
         ddd = (t - f[d]) + Real(dc);
         at(B.pos[d], o) = t;
-        int m = cnd;
-        if (m < 0) m += R.n[d];
-        else if (m >= R.n[d]) m -= R.n[d];
-        cw[d] = m;
+        cw[d] = wrap_step(cnd, R.n[d]);
       }
       // a drifting particle still bounds the next step's fixed-point scale
       if (kFix) mnew[d] = max(mnew[d], __float_as_int((float)fabs(ddd)));
       const int rn = rel[d] + (cnd - c[d]);
       bmin[d] = min(bmin[d], rn);
       bmax[d] = max(bmax[d], rn);
-      cwi += imul24(rn - jo_[d], jws[d]);
+      cwi += cwin(d, rn - jo_[d]);
     }
     if (kFix && DIM == 2) mnew[2] = max(mnew[2], __float_as_int((float)fabs(vd[2])));
     if (kCnt) atomicAdd(Cw + cwi, 1);
@@ -759,7 +766,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       for (int d = 0; d < DIM; ++d) {
         bmin[d] = min(bmin[d], rel[d]);
         bmax[d] = max(bmax[d], rel[d]);
-        cwi += imul24(rel[d] - jo_[d], jws[d]);
+        cwi += cwin(d, rel[d] - jo_[d]);
       }
       if (kCnt) atomicAdd(Cw + cwi, 1);
       continue;
@@ -1023,7 +1030,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       const int rn = rel[d] + (cn[d] - c[d]);
       bmin[d] = min(bmin[d], rn);
       bmax[d] = max(bmax[d], rn);
-      cwi += imul24(rn - jo_[d], jws[d]);
+      cwi += cwin(d, rn - jo_[d]);
     }
     if (kCnt) atomicAdd(Cw + cwi, 1);
     const unsigned os = fresh_off(o);
@@ -1034,10 +1041,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       int cw[3] = {0, 0, 0};
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        int m = cn[d];
-        if (m < 0) m += R.n[d];
-        else if (m >= R.n[d]) m -= R.n[d];
-        cw[d] = m;
+        cw[d] = wrap_step(cn[d], R.n[d]);
         at(B.pos[d], os) = fn[d];
       }
       at(B.cell, os) = pack_cell<DIM>(cw[0], cw[1], cw[2]);
