@@ -264,11 +264,18 @@ __device__ __forceinline__ void skip_axis_range(double a, double b, double lo, d
 
 }  // namespace
 
-// Workgroup size of the particle kernel: 2D tiles hold more particles.
-template <int DIM>
-constexpr int gpd_block() {
-  return DIM == 2 ? 512 : 256;
-}
+// Workgroup size and waves per SIMD of the particle kernel.  2D, and the
+// plain 3D kernel up to l = 2: 512 threads held to four waves per SIMD (two
+// groups per CU, at most 128 registers).  The 3D kernel with the partially
+// skipped calculation: 256 threads at three waves; the plain 3D kernel for
+// l >= 3 (more registers than four waves allow without heavy spilling):
+// 256 threads, unconstrained.
+template <int L, int DIM, bool SKIP>
+struct GpdShape {
+  static constexpr bool kWide = DIM == 2 || (!SKIP && L <= 2);
+  static constexpr int kBlock = kWide ? 512 : 256;
+  static constexpr int kWaves = kWide ? 4 : (SKIP ? 3 : 1);
+};
 
 template <class P, int L, int DIM, int KT, bool SKIP, int CP>
 __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
@@ -284,7 +291,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   constexpr Tab<Real> kWh = make_wtab<Real>(L, 0);
   constexpr Tab<Real> kWi = make_wtab<Real>(L, 1);
   const int tid = threadIdx.x;
-  const int nth = gpd_block<DIM>();
+  const int nth = GpdShape<L, DIM, SKIP>::kBlock;
 
   const int r = tile_run[g];
   const RunDev<Real>& R = runs[r];
@@ -502,8 +509,9 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // is rel = wrap(c - co, n) + lo, and it must lie in [rlo, rhi] for the
   // staged windows; window offsets of the half-lattice, T and union stencils
   // (kept in vector registers on the FP32 path, where scalar registers run
-  // out; the FP64 path needs its vector registers for its own state)
-  auto pin = [](int x) { return P::kAbs ? x : in_vgpr(x); };
+  // out; the FP64 path and the 512-thread 3D kernel need their vector
+  // registers for their own state, within 128 for four waves per SIMD)
+  auto pin = [](int x) { return (P::kAbs || (DIM == 3 && GpdShape<L, DIM, SKIP>::kWide)) ? x : in_vgpr(x); };
   int co[3], lo_[3], nn[3], rlo[3], rhi[3], hoff[3], toff[3], uoff[3], jo_[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -1162,14 +1170,15 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
 // Persistent workgroups: each takes tiles from a device queue until none are
 // left, so uneven tiles (edge tiles, runs of different size) balance.  The
 // queue starts at zero (set at initialisation, then rewound by the last
-// group of every launch).  In 2D every variant is held to four waves per
-// SIMD (two 512-thread workgroups per CU, at most 128 registers): a fifth
-// register block drops a wave and halves the workgroups a CU holds, which
-// costs far more than a few spilled values.  The 3D variant with the
-// partially skipped calculation is held to the plain kernel's three waves.
+// group of every launch).  Waves per SIMD and group size as GpdShape gives:
+// where the kernel is held to four waves per SIMD (two 512-thread groups per
+// CU, at most 128 registers), a fifth register block would drop a wave and
+// halve the groups a CU holds, which costs far more than a few spilled
+// values (3D, l = 2: 2.90 ms against 3.10 ms for three 256-thread groups of
+// 156 registers at 256x128x128).
 template <class P, int L, int DIM, bool SKIP, int CP>
-__global__ void __launch_bounds__(gpd_block<DIM>())
-__attribute__((amdgpu_waves_per_eu(DIM == 2 ? 4 : (SKIP ? 3 : 1))))
+__global__ void __launch_bounds__((GpdShape<L, DIM, SKIP>::kBlock))
+__attribute__((amdgpu_waves_per_eu(GpdShape<L, DIM, SKIP>::kWaves)))
     gpd_kernel(GpdArgs<typename P::Real> A, const RunDev<typename P::Real>* __restrict__ runs,
                const int* __restrict__ tile_run) {
   extern __shared__ __align__(16) unsigned char lds_dyn[];
@@ -1209,7 +1218,8 @@ static hipError_t launch_variant(const GpdArgs<typename P::Real>& a, size_t lds,
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((gpd_kernel<P, L, DIM, SKIP, CP>), dim3(grid), dim3(gpd_block<DIM>()), lds, s, a, a.runs,
+  hipLaunchKernelGGL((gpd_kernel<P, L, DIM, SKIP, CP>), dim3(grid), dim3(GpdShape<L, DIM, SKIP>::kBlock), lds, s,
+                     a, a.runs,
                      a.tile_run);
   return hipGetLastError();
 }
@@ -1383,7 +1393,8 @@ static int occupancy_one(size_t lds, bool skip) {
                        : reinterpret_cast<const void*>(&gpd_kernel<P, L, DIM, false, 0>);
   if (lds > 64 * 1024) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int n = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, gpd_block<DIM>(), lds);
+  const int block = skip ? GpdShape<L, DIM, true>::kBlock : GpdShape<L, DIM, false>::kBlock;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

@@ -670,8 +670,8 @@ int tuning_candidates(int ndim, bool f64, const Cand** out) {
                              {{32, 8, 1}, 3, 2},  {{32, 16, 1}, 2, 1}, {{16, 16, 1}, 2, 1}};
   static const Cand c2d[] = {{{16, 16, 1}, 3, 2}, {{16, 8, 1}, 3, 2}, {{32, 8, 1}, 3, 2},
                              {{8, 16, 1}, 3, 2},  {{32, 16, 1}, 3, 2}, {{16, 16, 1}, 2, 1}};
-  static const Cand c3s[] = {{{8, 4, 4}, 2, 1}, {{8, 8, 2}, 2, 1}, {{4, 4, 4}, 2, 1},
-                             {{16, 4, 4}, 2, 1}, {{8, 8, 4}, 2, 1}, {{8, 4, 4}, 3, 2}};
+  static const Cand c3s[] = {{{16, 4, 4}, 2, 1}, {{8, 8, 4}, 2, 1}, {{8, 4, 4}, 2, 1},
+                             {{8, 8, 2}, 2, 1},  {{4, 4, 4}, 2, 1}, {{16, 4, 4}, 3, 2}};
   static const Cand c3d[] = {{{4, 4, 4}, 2, 1}, {{8, 4, 4}, 2, 1}, {{4, 4, 2}, 2, 1}, {{8, 8, 2}, 2, 1},
                              {{4, 4, 4}, 3, 2}};
   if (ndim == 2) {
@@ -1002,9 +1002,10 @@ pic_status pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_buffers*
   static const int cand2s[][3] = {{32, 16, 1}, {16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}};
   static const int cand2d[][3] = {{16, 16, 1}, {16, 8, 1}, {8, 8, 1}, {8, 4, 1}, {4, 4, 1}, {4, 4, 1}};
   // 3D: FP64 takes the largest tile within half a CU's LDS (4x4x4); mixed
-  // precision keeps only its fine current windows in LDS, and 8x4x4 (47 KB,
-  // three groups per CU) measured 14% ahead of 8x8x4 (66 KB, two)
-  static const int cand3s[][3] = {{8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}, {2, 2, 2}};
+  // precision keeps only its fine current windows in LDS, and with 512-thread
+  // groups (two per CU, four waves per SIMD) 16x4x4 measured fastest at
+  // 256x128x128 (2.90 ms; 8x8x4 2.96, 8x4x4 3.26)
+  static const int cand3s[][3] = {{16, 4, 4}, {8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}};
   static const int cand3d[][3] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {4, 4, 2}, {4, 2, 2}, {2, 2, 2}};
   const int (*cand2)[3] = c->f64() ? cand2d : cand2s;
   const int (*cand3)[3] = c->f64() ? cand3d : cand3s;
