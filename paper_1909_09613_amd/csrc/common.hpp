@@ -57,6 +57,14 @@ __host__ __device__ inline void unpack_cell(int c, int& x, int& y, int& z) {
 constexpr int kFieldPitch2D = 64;
 constexpr int kCurrentPitch2D = 48;
 
+// Row and plane pitches of the 3D mixed-precision windows of at most 21 x 9
+// (fields) and 23 x 11 (current) nodes per plane: the windows of the default
+// 16 x 4 x 4 tile at l <= 2 and c dt <= dx/2.  As compile-time constants they
+// make every row and plane of a stencil an immediate LDS offset (one vector
+// add per row less, 2D and 3D alike); the planes keep the multiple of 8.
+constexpr int kFieldPitch3D[2] = {21, 192};
+constexpr int kCurrentPitch3D[2] = {23, 256};
+
 // Per-run constants, one entry per run in device memory.
 template <class Real>
 struct RunDev {

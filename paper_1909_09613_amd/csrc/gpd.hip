@@ -355,12 +355,15 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // windows: index x + row pitch * y + plane pitch * z (the pitches may
   // exceed the extents, so that the rows a wave reads at once spread over
   // the LDS banks)
-  // (CP > 0: the field row pitch is that compile-time constant and the
-  // current row pitch kCurrentPitch2D, so that the rows of a stencil are
-  // immediate offsets from one address)
-  const int fpx = CP > 0 ? CP : A.fp[0], fpz = A.fp[1];
+  // (CP = 1: the pitches are the compile-time constants of kFieldPitch2D,
+  // kCurrentPitch2D or kFieldPitch3D, kCurrentPitch3D, so that the rows and
+  // planes of a stencil are immediate offsets from one address)
+  constexpr bool kCP = CP != 0;
+  const int fpx = kCP ? (DIM == 2 ? kFieldPitch2D : kFieldPitch3D[0]) : A.fp[0];
+  const int fpz = (kCP && DIM == 3) ? kFieldPitch3D[1] : A.fp[1];
   const int fcap = (DIM == 3) ? fpz * A.fw[2] : fpx * A.fw[1];
-  const int jpx = CP > 0 ? kCurrentPitch2D : A.jp[0], jpz = A.jp[1];
+  const int jpx = kCP ? (DIM == 2 ? kCurrentPitch2D : kCurrentPitch3D[0]) : A.jp[0];
+  const int jpz = (kCP && DIM == 3) ? kCurrentPitch3D[1] : A.jp[1];
   const int jcap = (DIM == 3) ? jpz * A.jw[2] : jpx * A.jw[1];
   const long long NT = A.ncell_total;
   const Real* Fg = A.F + R.cell0;
@@ -1227,13 +1230,17 @@ static hipError_t launch_variant(const GpdArgs<typename P::Real>& a, size_t lds,
 template <class P, int L, int DIM>
 static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
   // the variant with the partially skipped calculation only where a run uses
-  // it (its extra registers would cost the plain step occupancy); 2D mixed
-  // precision windows of the constant row pitch take the variant compiled
-  // for it
+  // it (its extra registers would cost the plain step occupancy); mixed
+  // precision windows of the constant pitches take the variant compiled for
+  // them (in 3D for l <= 2, whose windows can have them)
   if constexpr (DIM == 2 && !P::kAbs) {
     if (a.fp[0] == kFieldPitch2D && a.jp[0] == kCurrentPitch2D)
-      return a.skip ? launch_variant<P, L, DIM, true, kFieldPitch2D>(a, lds, s)
-                    : launch_variant<P, L, DIM, false, kFieldPitch2D>(a, lds, s);
+      return a.skip ? launch_variant<P, L, DIM, true, 1>(a, lds, s) : launch_variant<P, L, DIM, false, 1>(a, lds, s);
+  }
+  if constexpr (DIM == 3 && !P::kAbs && L <= 2) {
+    if (a.fp[0] == kFieldPitch3D[0] && a.fp[1] == kFieldPitch3D[1] && a.jp[0] == kCurrentPitch3D[0] &&
+        a.jp[1] == kCurrentPitch3D[1])
+      return a.skip ? launch_variant<P, L, DIM, true, 1>(a, lds, s) : launch_variant<P, L, DIM, false, 1>(a, lds, s);
   }
   return a.skip ? launch_variant<P, L, DIM, true, 0>(a, lds, s) : launch_variant<P, L, DIM, false, 0>(a, lds, s);
 }

@@ -292,13 +292,20 @@ hipError_t host_copy(pic_ctx* c, void* dst, const void* src, size_t bytes, hipMe
 // to 64 nodes take a pitch of 64 and current rows of up to 48 a pitch of 48
 // (kFieldPitch2D, kCurrentPitch2D: 2% faster at 4096x2048 than 48 for both,
 // which was 1.8% faster than the bare 41); 3D planes a pitch rounded up to a
-// multiple of 8 (117 -> 120, 2% faster at 256x128x128: the LDS bank conflicts
-// of the wave's rows drop); padding the 3D rows instead costs a workgroup per
-// CU (the LDS of three groups no longer fits).
-void window_pitches(int ndim, bool f64, const int w[3], int row2d, int p[2]) {
+// multiple of 8 (117 -> 120, 2% faster at 256x128x128 with 8x4x4 tiles: the
+// LDS bank conflicts of the wave's rows drop), and 3D windows that fit the
+// compile-time pitches (kFieldPitch3D, kCurrentPitch3D; those of the default
+// 16x4x4 tile at l <= 2) take those.
+void window_pitches(int ndim, bool f64, const int w[3], int row2d, const int* fixed3d, int p[2]) {
   p[0] = (ndim == 2 && !f64 && w[0] <= row2d) ? row2d : w[0];
   p[1] = p[0] * w[1];
-  if (ndim == 3 && !f64) p[1] = (p[1] + 7) / 8 * 8;
+  if (ndim == 3 && !f64) {
+    p[1] = (p[1] + 7) / 8 * 8;
+    if (w[0] <= fixed3d[0] && fixed3d[0] * w[1] <= fixed3d[1]) {
+      p[0] = fixed3d[0];
+      p[1] = fixed3d[1];
+    }
+  }
 }
 
 // Reach of a table's nodes relative to the particle's cell: base - cell is 0
@@ -446,8 +453,8 @@ pic_status apply_tiling(pic_ctx* c) {
     c->jw[k] = c->guard[k] + 2 * (c->sort_every - 1) + span_d[k] + 1;
     if (c->guard[k] < c->tile[k]) return c->fail(PIC_ERR_ARG, "margin must exceed sort_every");
   }
-  window_pitches(nd, c->f64(), c->fw, kFieldPitch2D, c->fp);
-  window_pitches(nd, c->f64(), c->jw, kCurrentPitch2D, c->jp);
+  window_pitches(nd, c->f64(), c->fw, kFieldPitch2D, kFieldPitch3D, c->fp);
+  window_pitches(nd, c->f64(), c->jw, kCurrentPitch2D, kCurrentPitch3D, c->jp);
   const size_t fcap = (size_t)(nd == 3 ? c->fp[1] * c->fw[2] : c->fp[0] * c->fw[1]);
   const size_t jcap = (size_t)(nd == 3 ? c->jp[1] * c->jw[2] : c->jp[0] * c->jw[1]);
   const size_t rs = sizeof(Real);
