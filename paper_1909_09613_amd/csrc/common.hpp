@@ -46,24 +46,34 @@ __host__ __device__ inline void unpack_cell(int c, int& x, int& y, int& z) {
   }
 }
 
-// Row pitches (elements) of the 2D mixed-precision field and current windows
-// whenever they are at most this wide.  A compile-time pitch turns the rows of
-// a particle's stencil into immediate LDS offsets.  The LDS serves a wave's
-// 4-byte reads 32 lanes (one row of the wave's cells) at a time over 32
-// banks; the lanes whose T_l or W_l stencil starts one row lower read the
-// row above, which with a pitch of 64 (a multiple of 32) falls on other
-// banks than the rest of the half-wave's reads.  Current atomics showed no
-// such dependence, and their windows keep the smaller pitch 48.
-constexpr int kFieldPitch2D = 64;
-constexpr int kCurrentPitch2D = 48;
-
-// Row and plane pitches of the 3D mixed-precision windows of at most 21 x 9
-// (fields) and 23 x 11 (current) nodes per plane: the windows of the default
-// 16 x 4 x 4 tile at l <= 2 and c dt <= dx/2.  As compile-time constants they
-// make every row and plane of a stencil an immediate LDS offset (one vector
-// add per row less, 2D and 3D alike); the planes keep the multiple of 8.
-constexpr int kFieldPitch3D[2] = {21, 192};
-constexpr int kCurrentPitch3D[2] = {23, 256};
+// Compile-time window pitches (elements; row, and plane in 3D) of the
+// mixed-precision particle kernel's fixed-pitch variant, per dimension.  A
+// window that fits them is laid out with them (padded if smaller), and the
+// kernel then reads every row and plane of a stencil at an immediate LDS
+// offset from one address (one vector add per row less).  They are the
+// windows of the default tilings at the orders and Courant numbers of the
+// benchmark workloads:
+//  - 2D FP32 (32 x 16 tiles): field rows 64, current rows 48.  The LDS
+//    serves a wave's 4-byte reads 32 lanes (one row of the wave's cells) at
+//    a time over 32 banks; the lanes whose T_l or W_l stencil starts one row
+//    lower read the row above, which with a pitch of 64 (a multiple of 32)
+//    falls on other banks than the rest of the half-wave's reads.  Current
+//    atomics showed no such dependence.
+//  - 3D FP32 (16 x 4 x 4 tiles, l <= 2, c dt <= dx/2): fields 21 x 9 nodes
+//    per plane at (21, 192), current 23 x 11 at (23, 256) (planes rounded up
+//    to a multiple of 8).
+// (The same for the FP64 kernel measured no faster at 4096x2048 and 4%
+// slower at 256x128x128; it keeps its run-time pitches.)
+template <int DIM>
+struct FixedPitch;
+template <>
+struct FixedPitch<2> {
+  static constexpr int f[2] = {64, 0}, j[2] = {48, 0};
+};
+template <>
+struct FixedPitch<3> {
+  static constexpr int f[2] = {21, 192}, j[2] = {23, 256};
+};
 
 // Per-run constants, one entry per run in device memory.
 template <class Real>

@@ -355,15 +355,16 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // windows: index x + row pitch * y + plane pitch * z (the pitches may
   // exceed the extents, so that the rows a wave reads at once spread over
   // the LDS banks)
-  // (CP = 1: the pitches are the compile-time constants of kFieldPitch2D,
-  // kCurrentPitch2D or kFieldPitch3D, kCurrentPitch3D, so that the rows and
-  // planes of a stencil are immediate offsets from one address)
+  // (CP = 1: the pitches are the compile-time constants of FixedPitch, so
+  // that the rows and planes of a stencil are immediate offsets from one
+  // address)
   constexpr bool kCP = CP != 0;
-  const int fpx = kCP ? (DIM == 2 ? kFieldPitch2D : kFieldPitch3D[0]) : A.fp[0];
-  const int fpz = (kCP && DIM == 3) ? kFieldPitch3D[1] : A.fp[1];
+  using FP = FixedPitch<DIM>;
+  const int fpx = kCP ? FP::f[0] : A.fp[0];
+  const int fpz = (kCP && DIM == 3) ? FP::f[1] : A.fp[1];
   const int fcap = (DIM == 3) ? fpz * A.fw[2] : fpx * A.fw[1];
-  const int jpx = kCP ? (DIM == 2 ? kCurrentPitch2D : kCurrentPitch3D[0]) : A.jp[0];
-  const int jpz = (kCP && DIM == 3) ? kCurrentPitch3D[1] : A.jp[1];
+  const int jpx = kCP ? FP::j[0] : A.jp[0];
+  const int jpz = (kCP && DIM == 3) ? FP::j[1] : A.jp[1];
   const int jcap = (DIM == 3) ? jpz * A.jw[2] : jpx * A.jw[1];
   const long long NT = A.ncell_total;
   const Real* Fg = A.F + R.cell0;
@@ -1231,15 +1232,11 @@ template <class P, int L, int DIM>
 static hipError_t launch_one(const GpdArgs<typename P::Real>& a, size_t lds, hipStream_t s) {
   // the variant with the partially skipped calculation only where a run uses
   // it (its extra registers would cost the plain step occupancy); mixed
-  // precision windows of the constant pitches take the variant compiled for
-  // them (in 3D for l <= 2, whose windows can have them)
-  if constexpr (DIM == 2 && !P::kAbs) {
-    if (a.fp[0] == kFieldPitch2D && a.jp[0] == kCurrentPitch2D)
-      return a.skip ? launch_variant<P, L, DIM, true, 1>(a, lds, s) : launch_variant<P, L, DIM, false, 1>(a, lds, s);
-  }
-  if constexpr (DIM == 3 && !P::kAbs && L <= 2) {
-    if (a.fp[0] == kFieldPitch3D[0] && a.fp[1] == kFieldPitch3D[1] && a.jp[0] == kCurrentPitch3D[0] &&
-        a.jp[1] == kCurrentPitch3D[1])
+  // precision windows of the fixed pitches take the variant compiled for them
+  // (in 3D up to l = 2: larger orders have larger windows)
+  if constexpr (!P::kAbs && (DIM == 2 || L <= 2)) {
+    using FP = FixedPitch<DIM>;
+    if (a.fp[0] == FP::f[0] && a.jp[0] == FP::j[0] && (DIM == 2 || (a.fp[1] == FP::f[1] && a.jp[1] == FP::j[1])))
       return a.skip ? launch_variant<P, L, DIM, true, 1>(a, lds, s) : launch_variant<P, L, DIM, false, 1>(a, lds, s);
   }
   return a.skip ? launch_variant<P, L, DIM, true, 0>(a, lds, s) : launch_variant<P, L, DIM, false, 0>(a, lds, s);

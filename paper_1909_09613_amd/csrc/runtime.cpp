@@ -287,24 +287,24 @@ hipError_t host_copy(pic_ctx* c, void* dst, const void* src, size_t bytes, hipMe
   return e;
 }
 
-// Row and plane pitch of a staged window of w[0] x w[1] (x w[2]) nodes.
-// Measured on the benchmark workloads (mixed precision): 2D field rows of up
-// to 64 nodes take a pitch of 64 and current rows of up to 48 a pitch of 48
-// (kFieldPitch2D, kCurrentPitch2D: 2% faster at 4096x2048 than 48 for both,
-// which was 1.8% faster than the bare 41); 3D planes a pitch rounded up to a
-// multiple of 8 (117 -> 120, 2% faster at 256x128x128 with 8x4x4 tiles: the
-// LDS bank conflicts of the wave's rows drop), and 3D windows that fit the
-// compile-time pitches (kFieldPitch3D, kCurrentPitch3D; those of the default
-// 16x4x4 tile at l <= 2) take those.
-void window_pitches(int ndim, bool f64, const int w[3], int row2d, const int* fixed3d, int p[2]) {
-  p[0] = (ndim == 2 && !f64 && w[0] <= row2d) ? row2d : w[0];
+// Row and plane pitch of a staged window of w[0] x w[1] (x w[2]) nodes: in
+// mixed precision the fixed pitches of FixedPitch (fixed[2]: row, plane)
+// when the window fits them, so that the kernel's fixed-pitch variant runs;
+// else the window's own
+// row, and in 3D mixed precision a plane rounded up to a multiple of 8 (117
+// -> 120 nodes: 2% faster at 256x128x128 with 8x4x4 tiles, the LDS bank
+// conflicts of the wave's rows drop).  Measured on the benchmark workloads
+// (mixed precision): 2D field rows at 64 and current rows at 48 were 2%
+// faster at 4096x2048 than 48 for both, which was 1.8% faster than the bare
+// 41.
+void window_pitches(int ndim, bool f64, const int w[3], const int fixed[2], int p[2]) {
+  p[0] = w[0];
   p[1] = p[0] * w[1];
-  if (ndim == 3 && !f64) {
-    p[1] = (p[1] + 7) / 8 * 8;
-    if (w[0] <= fixed3d[0] && fixed3d[0] * w[1] <= fixed3d[1]) {
-      p[0] = fixed3d[0];
-      p[1] = fixed3d[1];
-    }
+  if (ndim == 3 && !f64) p[1] = (p[1] + 7) / 8 * 8;
+  const bool fits = !f64 && w[0] <= fixed[0] && (ndim == 2 || fixed[0] * w[1] <= fixed[1]);
+  if (fits) {
+    p[0] = fixed[0];
+    p[1] = (ndim == 2) ? p[0] * w[1] : fixed[1];
   }
 }
 
@@ -453,8 +453,10 @@ pic_status apply_tiling(pic_ctx* c) {
     c->jw[k] = c->guard[k] + 2 * (c->sort_every - 1) + span_d[k] + 1;
     if (c->guard[k] < c->tile[k]) return c->fail(PIC_ERR_ARG, "margin must exceed sort_every");
   }
-  window_pitches(nd, c->f64(), c->fw, kFieldPitch2D, kFieldPitch3D, c->fp);
-  window_pitches(nd, c->f64(), c->jw, kCurrentPitch2D, kCurrentPitch3D, c->jp);
+  const int* ffix = nd == 2 ? FixedPitch<2>::f : FixedPitch<3>::f;
+  const int* jfix = nd == 2 ? FixedPitch<2>::j : FixedPitch<3>::j;
+  window_pitches(nd, c->f64(), c->fw, ffix, c->fp);
+  window_pitches(nd, c->f64(), c->jw, jfix, c->jp);
   const size_t fcap = (size_t)(nd == 3 ? c->fp[1] * c->fw[2] : c->fp[0] * c->fw[1]);
   const size_t jcap = (size_t)(nd == 3 ? c->jp[1] * c->jw[2] : c->jp[0] * c->jw[1]);
   const size_t rs = sizeof(Real);
