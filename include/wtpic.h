@@ -213,7 +213,7 @@ pic_status pic_set_skip_region(pic_ctx *ctx, int32_t run, const double *lo, cons
 /* Tuning knobs (tile shape in cells, staging margin in cells, sort check
  * cadence in steps).  Any value <= 0 keeps the current choice (by default
  * the first of a measured list of tile shapes whose LDS fits half a CU: 2D
- * 32x16 in mixed precision, 16x16 in FP64; 3D 8x4x4 and 4x4x4).  Must be
+ * 32x16 in mixed precision, 16x16 in FP64; 3D 16x4x4 and 4x4x4).  Must be
  * called before the first step; returns PIC_ERR_STATE afterwards, and
  * PIC_ERR_ARG if the windows need more LDS than a workgroup can have
  * (160 KB), if margin <= sort_every, or if a tile has more than 4096 cells. */

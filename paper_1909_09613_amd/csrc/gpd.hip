@@ -395,7 +395,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   constexpr bool kCnt = kFix && DIM == 2;
   // 3D keeps its coarse (FP32) windows in a private region of global memory
   // (only the rare components above their bound touch them), so that its LDS
-  // leaves room for three groups per CU
+  // holds larger tiles at two groups per CU
   constexpr bool kGlobCoarse = kFix && DIM == 3;
   Real qinv[3] = {Real(0), Real(0), Real(0)}, thr[3] = {Real(0), Real(0), Real(0)};
   double qd[3] = {0.0, 0.0, 0.0};

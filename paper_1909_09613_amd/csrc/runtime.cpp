@@ -25,8 +25,8 @@ constexpr int kMaxLds = 160 * 1024;     // LDS of a gfx950 CU: the most one work
 constexpr int kMaxGroups = 2048;        // persistent particle-kernel groups (8 per CU of 256)
 constexpr int kCoarseCap = 3 * (kMaxLds / 12);  // ints of one group's coarse windows (3D mixed)
 // budget of the default tile choice: half a CU's LDS, so that two groups
-// share a CU (measured in 3D: 8x4x4 FP32 tiles at 69 KB and 4x4x4 FP64 tiles
-// at 67 KB beat the smaller tiles that fit 64 KB by 8% and 15%)
+// share a CU (measured in 3D: 16x4x4 FP32 tiles at 74 KB and 4x4x4 FP64
+// tiles at 67 KB beat the smaller tiles)
 constexpr int kDefaultLds = 80 * 1024;
 constexpr double kTuneMargin = 0.02;  // autotuner: relative gain needed to leave the default tiling
 constexpr int kMaxTileCells = 4096; // the sort orders a tile's cells in LDS
