@@ -944,14 +944,18 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         }
       } else {
         // path averages of the transverse shapes: (S0 + DS/2) and (S0/2 + DS/3)
-        // enter as S0_b (S0_c + DS_c/2) + DS_b (S0_c/2 + DS_c/3)
-        Real pa[3][NU], pb[3][NU];
+        // enter as S0_b (S0_c + DS_c/2) + DS_b (S0_c/2 + DS_c/3); the prefix
+        // sums run over DS scaled by the component's current scale, from the
+        // component's offset, so that a node's value is the running sum itself
+        const Real ks[3] = {kx, ky, kz};
+        Real pa[3][NU], pb[3][NU], dk[3][NU];
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
           for (int k = 0; k < NU; ++k) {
             pa[d][k] = S0u[d][k] + half * DSu[d][k];
             pb[d][k] = half * S0u[d][k] + third * DSu[d][k];
+            dk[d][k] = ks[d] * DSu[d][k];
           }
         // J1: prefix along x of DS_x * T_yz
 #pragma unroll
@@ -961,11 +965,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
             if ((v == L + 1 && !cross[1]) || (w == L + 1 && !cross[2])) continue;
             const Real tr = S0u[1][v] * pa[2][w] + DSu[1][v] * pb[2][w];
             const int ro = jpx * v + jpz * w;
-            Real acc = Real(0);
+            Real acc = ox;
 #pragma unroll
             for (int u = 0; u <= L; ++u) {
-              acc += DSu[0][u] * tr;
-              if (u < L || cross[0]) sink(0, jb + (ro + u), kFix ? fma(kx, acc, ox) : kx * acc);
+              acc += dk[0][u] * tr;
+              if (u < L || cross[0]) sink(0, jb + (ro + u), acc);
             }
           }
         }
@@ -977,11 +981,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
             if ((u == L + 1 && !cross[0]) || (w == L + 1 && !cross[2])) continue;
             const Real tr = S0u[0][u] * pa[2][w] + DSu[0][u] * pb[2][w];
             const int co = u + jpz * w;
-            Real acc = Real(0);
+            Real acc = oy;
 #pragma unroll
             for (int v = 0; v <= L; ++v) {
-              acc += DSu[1][v] * tr;
-              if (v < L || cross[1]) sink(1, jb + (co + jpx * v), kFix ? fma(ky, acc, oy) : ky * acc);
+              acc += dk[1][v] * tr;
+              if (v < L || cross[1]) sink(1, jb + (co + jpx * v), acc);
             }
           }
         }
@@ -993,11 +997,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
             if ((u == L + 1 && !cross[0]) || (v == L + 1 && !cross[1])) continue;
             const Real tr = S0u[0][u] * pa[1][v] + DSu[0][u] * pb[1][v];
             const int co = u + jpx * v;
-            Real acc = Real(0);
+            Real acc = oz;
 #pragma unroll
             for (int w = 0; w <= L; ++w) {
-              acc += DSu[2][w] * tr;
-              if (w < L || cross[2]) sink(2, jb + (co + jpz * w), kFix ? fma(kz, acc, oz) : kz * acc);
+              acc += dk[2][w] * tr;
+              if (w < L || cross[2]) sink(2, jb + (co + jpz * w), acc);
             }
           }
         }
