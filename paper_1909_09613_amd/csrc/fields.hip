@@ -66,8 +66,11 @@ __device__ __forceinline__ Real dbwd(const Grid3<Real>& g, int d, int i, int j, 
 // entries of the block table (256 cells of one run each) and computes every
 // new value before it stores any, so that the loads of its FR cells are in
 // flight together (the stores could alias the next cell's loads otherwise).
-// Four in FP32 and two in FP64; one for the wide M4 stencil, whose loads
-// would otherwise take the registers of most of the waves.
+// For the Yee Faraday update four in FP32 and two in FP64; one for the wide
+// M4 stencil, whose loads would otherwise take the registers of most of the
+// waves, and one for the Ampere update, whose fifteen arrays per cell keep
+// enough loads in flight (measured at 4096x2048: two or four cells per
+// thread there cost 1-3%).
 template <class Real, bool WIDE>
 constexpr int cells_per_thread() {
   return WIDE ? 1 : (sizeof(Real) == 4 ? 4 : 2);
@@ -119,7 +122,7 @@ __global__ void __launch_bounds__(256) faraday_kernel(FieldArgs<Real> A) {
 // E <- E + dt (c curl B - J); J <- 0 for the next deposit.
 template <class Real, int DIM>
 __global__ void __launch_bounds__(256) ampere_kernel(FieldArgs<Real> A) {
-  constexpr int FR = cells_per_thread<Real, false>();
+  constexpr int FR = cells_per_thread<Real, true>();
   const long long NT = A.ncell_total;
   Real ne[FR][3];
   Real* out[FR];
@@ -194,7 +197,7 @@ hipError_t launch_faraday_half(const FieldArgs<Real>& a, int ndim, bool m4, hipS
 template <class Real>
 hipError_t launch_ampere(const FieldArgs<Real>& a, int ndim, hipStream_t s) {
   if (a.nblocks <= 0) return hipSuccess;
-  const int fr = cells_per_thread<Real, false>();
+  const int fr = cells_per_thread<Real, true>();
   const dim3 grid((a.nblocks + fr - 1) / fr), blk(256);
   if (ndim == 2)
     hipLaunchKernelGGL((ampere_kernel<Real, 2>), grid, blk, 0, s, a);
