@@ -208,6 +208,46 @@ def test_field_update(orc, ndim, solver, aniso, precision):
     assert max(H.rel_maxnorm(Bg, g.B)) <= tol
 
 
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("solver", [0, 1], ids=["yee", "m4"])
+@pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32], ids=["fp64", "fp32"])
+def test_field_update_batched(orc, ndim, solver, precision):
+    """Runs of different sizes in one context: the field update's blocks of
+    256 cells end at run boundaries, a thread computes cells of several
+    blocks (of different runs, and past the last block), and every run
+    matches its own oracle grid after three updates."""
+    sizes = ([(20, 17), (13, 9), (31, 5), (40, 24), (7, 5)] if ndim == 2
+             else [(12, 10, 9), (5, 7, 5), (9, 5, 6)])
+    specs = [RunSpec(ndim, n, 2, 0.4, 50.0, 0.01, 1, 500 + k, solver=solver) for k, n in enumerate(sizes)]
+    rng = np.random.default_rng(9)
+    sim = wt.Sim(specs, precision)
+    try:
+        grids = []
+        for r, spec in enumerate(specs):
+            E = inputs.random_fields(rng, spec.ncell, 1.0)
+            B = inputs.random_fields(rng, spec.ncell, 1.0)
+            if precision == wt.PIC_MIXED32:
+                E = E.astype(np.float32).astype(np.float64)
+                B = B.astype(np.float32).astype(np.float64)
+            g = H.oracle_grid(orc, spec)
+            g.E[:] = E
+            g.B[:] = B
+            grids.append(g)
+            sim.set_species(r, inputs.make_species(spec))
+            sim.set_fields(r, E, B)
+        for _ in range(3):
+            sim.field_update()
+            for g in grids:
+                g.field_update()
+        tol = 1e-13 if precision == wt.PIC_FP64 else 3e-6
+        for r, g in enumerate(grids):
+            Eg, Bg, _ = sim.fields(r)
+            assert max(H.rel_maxnorm(Eg, g.E)) <= tol, r
+            assert max(H.rel_maxnorm(Bg, g.B)) <= tol, r
+    finally:
+        sim.close()
+
 def test_config1_trajectory_fp64(orc):
     """The 64x64 correctness workload (l = 2, c dt = 0.7 dx, 4 ppc/species,
     gamma 50) for 100 full steps from the loader's state, against the oracle.
