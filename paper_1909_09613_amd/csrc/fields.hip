@@ -1,7 +1,7 @@
 // Maxwell update (Yee leapfrog, or the Faraday stencil of Appendix C) and the
 // FP64 diagnostics reductions.  These stencils are HBM-bound and small next
-// to the particle kernel; one thread per cell, every run of a context in one
-// launch (a block never straddles two runs).
+// to the particle kernel; every run of a context in one launch, over a table
+// of 256-cell blocks that never straddle two runs.
 #include "common.hpp"
 #include "launch.hpp"
 
