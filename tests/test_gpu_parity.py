@@ -99,6 +99,8 @@ CASES_3D = [
     RunSpec(3, (12, 12, 12), 3, 0.35, 50.0, 0.01, 1, 23),
     RunSpec(3, (14, 12, 10), 2, 0.3, 50.0, 0.01, 2, 24, dx=(1.0, 0.8, 1.25)),  # anisotropic cells
     RunSpec(3, (12, 14, 16), 2, 0.45, 50.0, 0.01, 2, 25, drift_axis=2),        # the beam along x3
+    RunSpec(3, (12, 10, 10), 2, 0.55, 10.0, 0.1, 2, 26),                       # a > 1/2: l+2 T nodes
+    RunSpec(3, (12, 12, 10), 4, 0.3, 50.0, 0.01, 1, 27),                       # quartic
 ]
 
 
