@@ -36,6 +36,9 @@ CASES = {
     "cold-start-strong-fields": (RunSpec(3, (14, 12, 10), 2, 0.45, 1.0, 0.001, 2, 202, colocated=False,
                                          skin_depth_cells=4.0), 0.3, 24),
     "beam-along-x3": (RunSpec(3, (12, 12, 18), 2, 0.5, 50.0, 0.01, 2, 203, drift_axis=2), 0.002, 24),
+    # the 256-thread kernel of the higher orders, and l + 2 T nodes
+    "cubic": (RunSpec(3, (12, 12, 12), 3, 0.35, 50.0, 0.01, 1, 204), 0.002, 20),
+    "a-above-half": (RunSpec(3, (12, 10, 10), 2, 0.55, 10.0, 0.1, 2, 205), 0.002, 20),
 }
 
 
