@@ -111,3 +111,39 @@ def current_tol(spec, k, fp32):
         return 1e-5
     step = 0.8 * spec.courant * spec.u_th / spec.gamma0
     return max(2e-4, 2.0 ** -25 / step)
+
+
+def trajectory_vs_oracle(orc, spec, amp, steps, precision, seed=11):
+    """`steps` graph-replayed steps (pic_step) of one run from a seeded
+    random state with fields of amplitude `amp`, and the same steps of the
+    oracle.  Returns the particle position and momentum errors, the E and B
+    relative max-norm errors and the number of sorts the device made; asserts
+    that no particle was counted non-finite or out of its window."""
+    import paper_1909_09613_amd as wt
+    fp32 = precision == wt.PIC_MIXED32
+    sp, E, B = random_state(spec, seed, amp, fp32=fp32)
+    g = oracle_grid(orc, spec)
+    g.E[:] = E
+    g.B[:] = B
+    ref = copy_species(sp)
+    sim = wt.Sim([spec], precision)
+    try:
+        sim.set_species(0, sp)
+        sim.set_fields(0, E, B)
+        d0 = sim.diagnostics(0)
+        sim.step(steps)
+        d = sim.diagnostics(0)
+        got = [sim.particles(0, s) for s in range(2)]
+        Eg, Bg, _ = sim.fields(0)
+    finally:
+        sim.close()
+    for _ in range(steps):
+        g.step(ref)
+    ex, eu = particle_errors(spec, ref, got)
+    eE = max(rel_maxnorm(Eg, g.E))
+    eB = max(rel_maxnorm(Bg, g.B))
+    print("%dD l=%d %d steps %s: dx=%.2e du=%.2e dE=%.2e dB=%.2e sorts=%d" % (
+        spec.ndim, spec.order, steps, "fp32" if fp32 else "fp64", ex, eu, eE, eB, d.n_sorts - d0.n_sorts),
+        flush=True)
+    assert d.n_nonfinite == 0 and d.n_out_of_range == 0
+    return ex, eu, eE, eB, d.n_sorts - d0.n_sorts

@@ -17,15 +17,13 @@ the next:
 
 Bounds: FP64 positions 1e-12 cells, momenta 1e-12 relative, E and B 1e-12
 relative max-norm.  Mixed precision starts from an FP32-representable state
-and rounds to FP32 every step (~2e-6 per step, the one-step bound); over 24-32
+and rounds to FP32 every step (~2e-6 per step, the one-step bound); over 20-32
 steps that accumulates to at most ~1e-4 in positions and momenta, and the
 fields, which sum the currents of all steps, to 1e-3 relative max-norm.
 """
-import numpy as np
 import pytest
 
 import paper_1909_09613_amd as wt
-from paper_1909_09613_amd import inputs
 from paper_1909_09613_amd.inputs import RunSpec
 from tests import helpers as H
 
@@ -42,40 +40,11 @@ CASES = {
 }
 
 
-def _trajectory(orc, spec, amp, steps, precision):
-    fp32 = precision == wt.PIC_MIXED32
-    sp, E, B = H.random_state(spec, 11, amp, fp32=fp32)
-    g = H.oracle_grid(orc, spec)
-    g.E[:] = E
-    g.B[:] = B
-    ref = H.copy_species(sp)
-    sim = wt.Sim([spec], precision)
-    try:
-        sim.set_species(0, sp)
-        sim.set_fields(0, E, B)
-        d0 = sim.diagnostics(0)
-        sim.step(steps)
-        d = sim.diagnostics(0)
-        got = [sim.particles(0, s) for s in range(2)]
-        Eg, Bg, _ = sim.fields(0)
-    finally:
-        sim.close()
-    for _ in range(steps):
-        g.step(ref)
-    ex, eu = H.particle_errors(spec, ref, got)
-    eE = max(H.rel_maxnorm(Eg, g.E))
-    eB = max(H.rel_maxnorm(Bg, g.B))
-    print("3D %d steps %s: dx=%.2e du=%.2e dE=%.2e dB=%.2e sorts=%d" % (
-        steps, "fp32" if fp32 else "fp64", ex, eu, eE, eB, d.n_sorts - d0.n_sorts), flush=True)
-    assert d.n_nonfinite == 0 and d.n_out_of_range == 0
-    return ex, eu, eE, eB, d.n_sorts - d0.n_sorts
-
-
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("precision", [wt.PIC_FP64, wt.PIC_MIXED32], ids=["fp64", "fp32"])
 def test_3d_multistep_against_oracle(orc, case, precision):
     spec, amp, steps = CASES[case]
-    ex, eu, eE, eB, sorts = _trajectory(orc, spec, amp, steps, precision)
+    ex, eu, eE, eB, sorts = H.trajectory_vs_oracle(orc, spec, amp, steps, precision)
     if precision == wt.PIC_FP64:
         assert ex <= 1e-12 and eu <= 1e-12
         assert eE <= 1e-12 and eB <= 1e-12
