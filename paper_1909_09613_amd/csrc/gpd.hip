@@ -98,6 +98,39 @@ __device__ __forceinline__ Real gather3(const Real* Fc, int px, int pz, const Re
   return s;
 }
 
+// Weights of a B-spline table's NW nodes at g.  The cubic B-spline of the
+// compile-time tables in its symmetric closed form, 11 instructions against
+// 12 for the four Horner polynomials: with t = 1 - g, w0 = t^3/6,
+// w1 = 2/3 - g^2 + g^3/2, w2 the same at t, w3 = g^3/6 (the coefficients of
+// those tables, checked where they are built).
+template <int L, int NW, bool CONSTTAB, class Real>
+__device__ __forceinline__ void wtab_eval(const Tab<Real>& T, Real g, Real* w) {
+  if constexpr (CONSTTAB && L == 3 && NW == 4) {
+    const Real t = Real(1) - g;
+    const Real g2 = g * g, t2 = t * t;
+    w[0] = t2 * (t * Real(1.0 / 6.0));
+    w[1] = fma(g2, fma(g, Real(0.5), Real(-1)), Real(2.0 / 3.0));
+    w[2] = fma(t2, fma(t, Real(0.5), Real(-1)), Real(2.0 / 3.0));
+    w[3] = g2 * (g * Real(1.0 / 6.0));
+  } else {
+    tab_eval<L, NW, false>(T, g, w);
+  }
+}
+
+// Whether a table holds the cubic B-spline polynomials in the node order of
+// wtab_eval's closed form.
+template <class Real>
+constexpr bool is_cubic_bspline(const Tab<Real>& t) {
+  constexpr double ref[4][4] = {{1.0 / 6, -0.5, 0.5, -1.0 / 6}, {2.0 / 3, 0.0, -1.0, 0.5},
+                                {1.0 / 6, 0.5, 0.5, -0.5}, {0.0, 0.0, 0.0, 1.0 / 6}};
+  for (int k = 0; k < 4; ++k)
+    for (int r = 0; r < 4; ++r) {
+      const double d = (double)t.c[k][r] - ref[k][r];
+      if (d > 1e-6 || d < -1e-6) return false;
+    }
+  return true;
+}
+
 template <class Real>
 __device__ __forceinline__ bool finite3(Real a, Real b, Real c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
@@ -290,6 +323,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
   // B-spline tables on the half-integer and the integer lattice: constants
   constexpr Tab<Real> kWh = make_wtab<Real>(L, 0);
   constexpr Tab<Real> kWi = make_wtab<Real>(L, 1);
+  static_assert(L != 3 || (is_cubic_bspline(kWh) && is_cubic_bspline(kWi)), "cubic tables");
   const int tid = threadIdx.x;
   const int nth = GpdShape<L, DIM, SKIP>::kBlock;
 
@@ -697,7 +731,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       int b;
       Real gg;
       tab_split(Th, c[d], f[d], b, gg);
-      tab_eval<L, NW, false>(Th, gg, wh[d]);
+      wtab_eval<L, NW, kFix>(Th, gg, wh[d]);
       ih[d] = rel[d] + (b - c[d]) + hoff[d];
     };
 #pragma unroll
@@ -827,7 +861,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       tab_split(Tw, c[d], f[d], b0, g0);
       tab_split(Tw, cn[d], fn[d], b1, g1);
       Real s0[NW], s1[NW], dA[NW], dB[NW], a0[NU], ds[NU];
-      tab_eval<L, NW, false>(Tw, g0, s0);
+      wtab_eval<L, NW, kFix>(Tw, g0, s0);
       const int db = b1 - b0;
       cross[d] = db != 0;
       const bool shA = db < 0, shB = db > 0;
@@ -838,7 +872,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
       if (__all(fabs(dd[d]) >= Real(0.0625))) {
         // every step of the wave is long: S1 - S0 directly keeps its
         // precision (rounding of order one against |step| >= 1/16)
-        tab_eval<L, NW, false>(Tw, g1, s1);
+        wtab_eval<L, NW, kFix>(Tw, g1, s1);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
           a0[k] = shA ? (k >= 1 ? s0[k - 1] : Real(0)) : (k < NW ? s0[k] : Real(0));
