@@ -117,6 +117,27 @@ __device__ __forceinline__ void wtab_eval(const Tab<Real>& T, Real g, Real* w) {
   }
 }
 
+// Weight differences w_k(e) - w_k(g) = d * (divided difference), d = e - g,
+// for a table's L + 1 nodes.  For the cubic B-spline of the compile-time
+// tables with h2 = g + e and h3 = g^2 + g e + e^2: the differences of the
+// four closed forms above are d (h3/6), d ((h2 - 1)/2 - h3/6) and
+// d (h3/2 - h2) for nodes 3, 0 and 1, and node 2 takes minus their sum (the
+// weights sum to one), 12 instructions against 16.
+template <int L, bool CONSTTAB, class Real>
+__device__ __forceinline__ void wtab_diff(const Tab<Real>& T, Real g, Real e, Real d, Real* dw) {
+  if constexpr (CONSTTAB && L == 3) {
+    const Real h2 = g + e;
+    const Real h3 = fma(h2, e, g * g);
+    const Real q = h3 * (d * Real(1.0 / 6.0));
+    dw[3] = q;
+    dw[0] = fma(h2 - Real(1), d * Real(0.5), -q);
+    dw[1] = fma(Real(3), q, -(d * h2));
+    dw[2] = -(dw[0] + dw[1]) - q;
+  } else {
+    tab_diff<L, CONSTTAB>(T, g, e, d, dw);
+  }
+}
+
 // Whether a table holds the cubic B-spline polynomials in the node order of
 // wtab_eval's closed form.
 template <class Real>
@@ -881,7 +902,7 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         }
       } else if (!__any(db != 0)) {
         // no lane of the wave changed its stencil: one divided difference
-        tab_diff<L, kFix>(Tw, g0, g1, dd[d], dA);
+        wtab_diff<L, kFix>(Tw, g0, g1, dd[d], dA);
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
           a0[k] = k < NW ? s0[k] : Real(0);
@@ -892,11 +913,11 @@ __device__ __forceinline__ void gpd_tile(const GpdArgs<typename P::Real>& A,
         // it crossed (an end of g's range)
         const Real eA = (db == 0) ? g1 : (db > 0 ? Real(1) : Real(0));
         const Real lA = (db == 0) ? dd[d] : (db > 0 ? Real(1) - g0 : -g0);
-        tab_diff<L, kFix>(Tw, g0, eA, lA, dA);
+        wtab_diff<L, kFix>(Tw, g0, eA, lA, dA);
         if (db != 0) {
           const Real sBv = (db > 0) ? Real(0) : Real(1);
           const Real lB = (db > 0) ? g1 : g1 - Real(1);
-          tab_diff<L, kFix>(Tw, sBv, g1, lB, dB);
+          wtab_diff<L, kFix>(Tw, sBv, g1, lB, dB);
         } else {
 #pragma unroll
           for (int k = 0; k < NW; ++k) dB[k] = Real(0);
